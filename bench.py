@@ -1,0 +1,218 @@
+"""Benchmark: Wilson-Dirac solves on one MI355X.
+
+Default workload (one "step" = one whole solve): plain FP64 even-odd BiCGStab on a
+32^3x64 lattice, links exp(i*0.3*A), kappa = 0.125, a complex Gaussian source per step,
+relative residual 1e-10 (checked in FP64 after the iteration).  Sources and links are
+resident in HBM before the timed region starts.
+
+Printed: one JSON line with solves/s (value), p50/p99 latency, the achieved bandwidth of
+the dominant kernel (the parity hop, measured with HIP events on the library's stream
+over the timed region) against the MI355X HBM peak, a Dslash-only figure (parity hop
+alone), and the CPU oracle timed on a bounded sample of the same workload.
+
+Other workloads (not the headline line): --workload mixed48 | batched24 | small8 | dslash.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GB/s & % HBM roofline; solves/s + p99 latency at rel. residual 1e-10"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="fp64_32")
+    p.add_argument("--dslash-reps", type=int, default=50)
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-cpu", action="store_true")
+    return p.parse_args()
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+WORKLOADS = {
+    # name: (dims, kappa, tol, precision, nrhs, description)
+    "fp64_32": ((32, 32, 32, 64), 0.125, 1e-10, 0, 1,
+                "plain FP64 even-odd BiCGStab, 32^3x64, kappa=0.125, eps=0.3, tol=1e-10"),
+    "small8": ((8, 8, 8, 8), 0.12, 1e-10, 0, 1, "plain FP64 even-odd BiCGStab, 8^4, kappa=0.12, tol=1e-10"),
+    "mixed48": ((48, 48, 48, 96), 0.125, 1e-10, 1, 1,
+                "mixed precision (FP32 inner, FP64 outer) even-odd BiCGStab, 48^3x96, kappa=0.125, tol=1e-10"),
+    "mixed48_fp16": ((48, 48, 48, 96), 0.125, 1e-10, 3, 1,
+                     "mixed precision (FP16 spinors + per-site scale, FP32 links inner; FP64 outer), 48^3x96"),
+    "batched24": ((24, 24, 24, 48), 0.125, 1e-10, 1, 12,
+                  "12 point sources in one batched solve, FP32 inner / FP64 outer, 24^3x48, kappa=0.125"),
+}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (see the design notes on "
+              "how the lattice would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1811_00893_amd import _lib as L
+    from paper_1811_00893_amd import counts, inputs
+
+    dims, kappa, tol, precision, nrhs, desc = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    V = int(np.prod(dims))
+    Vh = V // 2
+    t_setup = time.perf_counter()
+    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=dev)
+    nsrc = args.steps + args.warmup
+    if nrhs == 1:
+        srcs = [inputs.gaussian_source(dims, seed=2002 + i, device=dev) for i in range(nsrc)]
+    else:
+        pts = inputs.point_sources(dims, device=dev)
+        srcs = [pts for _ in range(nsrc)]
+    x = torch.zeros_like(srcs[0])
+    ctx = L.wilson_context_create()
+    gbits = L.WILSON_GAUGE_FP32 | (L.WILSON_GAUGE_FP16 if precision == 2 else 0)
+    g = L.wilson_gauge_load(ctx, U, dims, gbits)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    opts = {"precision": precision, "maxiter": 20000}
+
+    # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload) ----
+    dprec = 0 if precision == 0 else 1
+    psi = srcs[0] if nrhs == 1 else srcs[0][0].contiguous()
+    out = torch.zeros_like(psi)
+    for _ in range(3):
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec), "dslash")
+    torch.cuda.synchronize()
+    L.wilson_timing_enable(ctx, True)
+    for _ in range(args.dslash_reps):
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec), "dslash")
+    torch.cuda.synchronize()
+    d_ms, d_n, d_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
+    L.wilson_timing_enable(ctx, False)
+    d_us = 1e3 * d_ms / max(d_n, 1)
+    d_gbs = d_bytes / (d_ms * 1e-3) / 1e9
+    sname = "fp64" if dprec == 0 else "fp32"
+    dslash = {
+        "precision": sname,
+        "us_per_launch": d_us,
+        "launches": d_n,
+        "algorithmic_bytes_per_launch": d_bytes / max(d_n, 1),
+        "bytes_per_site": counts.hop_bytes_per_site(sname),
+        "gbs": d_gbs,
+        "frac_hbm_peak": d_gbs / counts.MI355X_HBM_GBS,
+        "gflops": counts.HOP_FLOPS_PER_SITE * Vh / (d_us * 1e-6) / 1e9,
+        "working_set_mb": d_bytes / max(d_n, 1) / 1e6,
+    }
+
+    # ---- solves ----
+    kap = [kappa] * nrhs
+    tl = [tol] * nrhs
+    for i in range(args.warmup):
+        x.zero_()
+        st, info = L.wilson_solve_ex(ctx, g, x, srcs[i], nrhs, kap, tl, opts)
+        L.check(st, "warmup solve")
+    torch.cuda.synchronize()
+    lat, iters, res, cycles = [], [], [], []
+    L.wilson_timing_enable(ctx, True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        st, info = L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, opts)
+        lat.append(time.perf_counter() - s0)
+        if st != 0:
+            raise RuntimeError(f"solve {i} returned {st}: {L.wilson_last_error()}")
+        iters.append(max(d["iterations"] for d in info))
+        cycles.append(max(d["outer_cycles"] for d in info))
+        res.append(max(d["true_residual"] for d in info))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    h_ms, h_n, h_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
+    b_ms, b_n, b_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_BLAS)
+    L.wilson_timing_enable(ctx, False)
+    solves = args.steps * nrhs
+    hop_gbs = h_bytes / (h_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "parity hop (all hop launches of the timed solves)",
+        "achieved": hop_gbs,
+        "peak": counts.MI355X_HBM_GBS,
+        "unit": "GB/s",
+        "frac": hop_gbs / counts.MI355X_HBM_GBS,
+        "traffic": None,
+        "launches": h_n,
+        "us_per_launch": 1e3 * h_ms / max(h_n, 1),
+        "algorithmic_bytes_per_launch": h_bytes / max(h_n, 1),
+        "hop_time_fraction": h_ms / (total * 1e3),
+        "blas_gbs": b_bytes / (b_ms * 1e-3) / 1e9 if b_ms > 0 else None,
+    }
+
+    # ---- CPU oracle on a bounded sample of the same workload ----
+    cpu = None
+    if not args.no_cpu and nrhs == 1:
+        import oracle
+        Un = U.cpu().numpy()
+        bn = srcs[0].cpu().numpy()
+        xo = np.zeros_like(bn)
+        t1 = time.perf_counter()
+        oracle.solve(bn, Un, kappa, dims, 0.0, 1, "bicgstab_eo", x0=xo)
+        one = time.perf_counter() - t1
+        k_it = max(1, min(50, int(args.cpu_seconds / max(one, 1e-3))))
+        t1 = time.perf_counter()
+        oracle.solve(bn, Un, kappa, dims, 0.0, k_it, "bicgstab_eo", x0=xo)
+        el = time.perf_counter() - t1
+        per_iter = el / k_it
+        it_per_solve = float(np.median(iters))
+        cpu = {
+            "value": 1.0 / (per_iter * it_per_solve),
+            "unit": "solves/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{k_it} even-odd BiCGStab iterations of the FP64 oracle on the same {dims} problem "
+                      f"({el:.1f} s), scaled by the {it_per_solve:.0f} iterations the GPU solve needs",
+            "seconds_per_iteration": per_iter,
+        }
+        del Un
+
+    line = {
+        "metric": METRIC,
+        "value": solves / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "lattice": list(dims), "kappa": kappa, "tol": tol, "eps": 0.3,
+                   "nrhs": nrhs, "precision": ["fp64", "mixed_fp32", "mixed_fp16", "mixed_fp16_l32"][precision]},
+        "p50_ms": 1e3 * percentile(lat, 50),
+        "p99_ms": 1e3 * percentile(lat, 99),
+        "iterations_median": float(np.median(iters)),
+        "outer_cycles_median": float(np.median(cycles)),
+        "true_residual_max": max(res),
+        "dslash": dslash,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "setup_s": setup_s,
+    }
+    L.wilson_gauge_free(ctx, g)
+    L.wilson_context_destroy(ctx)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

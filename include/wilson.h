@@ -1,0 +1,233 @@
+/*
+ * wilson.h -- C ABI of the MI355X (gfx950) Wilson-Dirac operator and solver library.
+ *
+ * The operator is the Wilson fermion matrix of Kanamori & Matsufuru, Sec. 2.1, Eq. (1):
+ *
+ *   D(x,y) = delta_{x,y} - kappa * sum_{mu=1..4} [ (1 - gamma_mu) U_mu(x) delta_{x+mu,y}
+ *                                                + (1 + gamma_mu) U_mu(x-mu)^dag delta_{x-mu,y} ]
+ *          = 1 - kappa * H,
+ *
+ * acting on complex fields with 4 spin x 3 colour components per site (Sec. 2, "The
+ * fermion field ... 12 degrees of freedom on each site"), with SU(3) links U_mu(x) on
+ * the 4 directions.  The linear system D x = b is solved with a Krylov method
+ * (BiCGStab, Sec. 2 "We employ the BiCGStab algorithm"), here on the even-odd
+ * preconditioned Schur system, with CG on the normal equations as a second method and
+ * a mixed-precision (FP32 / FP16 inner, FP64 outer) variant (Sec. 2: a single-precision
+ * inner solver of a mixed-precision solver governs the cost of the whole solve).
+ *
+ * CONVENTIONS (all entry points)
+ *   dims  = {Lx, Ly, Lz, Lt}; every extent even and >= 2.  V = Lx*Ly*Lz*Lt.
+ *   site  s = x + Lx*(y + Ly*(z + Lz*t)), 0-based; parity of a site = (x+y+z+t) mod 2.
+ *   mu    = 0..3 <-> x, y, z, t.
+ *   Complex numbers are interleaved (re, im) doubles (double _Complex layout).
+ *   Spinor element (s, spin, colour) is complex number (s*4 + spin)*3 + colour
+ *     (12*V complex = 24*V doubles per field; nrhs fields are stored back to back).
+ *   Link U_mu(s)[a][b] is complex number ((s*4 + mu)*3 + a)*3 + b (36*V complex).
+ *   gamma_mu in the Dirac basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = x,y,z),
+ *     gamma_t = diag(1, 1, -1, -1); gamma_5 = gamma_x gamma_y gamma_z gamma_t.
+ *   Boundaries: periodic in x, y, z; antiperiodic in t.  The caller passes periodic
+ *     links; the library applies the sign -1 to the hops that cross t = Lt-1 <-> 0.
+ *
+ * POINTERS AND OWNERSHIP
+ *   Every buffer is owned by the caller.  Array arguments may be host or device memory
+ *   (detected per pointer).  With device pointers the call is enqueued on the context's
+ *   stream and returns without waiting, except where stated; with host pointers the
+ *   call copies through device memory and returns when the result is on the host.
+ *   The library keeps no caller pointer after a call returns.  Handles (contexts,
+ *   gauge fields, batches) are owned by the library and released by their _free /
+ *   _destroy call.  A context and everything created from it is used by one host thread
+ *   at a time; distinct contexts may be used concurrently.
+ *
+ * ERRORS
+ *   Every int-returning call returns a wilson_status code; no C++ exception crosses
+ *   the ABI.  wilson_strerror() gives text, wilson_last_error() the detail of the last
+ *   failure on the calling thread.
+ */
+#ifndef WILSON_H
+#define WILSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WILSON_OK = 0,
+    WILSON_NOT_CONVERGED = 1,  /* x holds the last iterate; info is filled */
+    WILSON_INVALID_ARG = -1,   /* null, odd or < 2 extent, bad kappa/tol/maxiter/parity, ... */
+    WILSON_OUT_OF_MEMORY = -2,
+    WILSON_DEVICE_ERROR = -3,  /* a HIP call failed; see wilson_last_error() */
+    WILSON_BREAKDOWN = -4,     /* Krylov breakdown persisted through restarts */
+    WILSON_NONFINITE = -5,     /* NaN or Inf in the input or an iterate */
+    WILSON_REJECTED = -6,      /* admission refused (memory budget) */
+    WILSON_BUSY = -7           /* batch slot occupied / not ready */
+} wilson_status;
+
+/* Arithmetic/storage precision of spinors and links inside the library. */
+typedef enum {
+    WILSON_FP64 = 0,      /* FP64 spinors and links */
+    WILSON_FP32 = 1,      /* FP32 spinors and links, FP64 reduction accumulators */
+    WILSON_FP16 = 2,      /* FP16 spinors with one FP32 scale per site, FP16 links */
+    WILSON_FP16_L32 = 3   /* FP16 spinors with one FP32 scale per site, FP32 links */
+} wilson_precision;
+
+/* Bits of wilson_gauge_load's `precisions`: which link copies to keep resident. */
+#define WILSON_GAUGE_FP64 1u
+#define WILSON_GAUGE_FP32 2u
+#define WILSON_GAUGE_FP16 4u
+
+typedef enum {
+    WILSON_SOLVER_BICGSTAB_EO = 0, /* BiCGStab on M_ee = 1 - kappa^2 H_eo H_oe */
+    WILSON_SOLVER_CGNR_EO = 1      /* CG on M_ee^dag M_ee (CGLS form), M_ee^dag = g5 M_ee g5 */
+} wilson_solver;
+
+typedef struct wilson_ctx wilson_ctx;
+typedef struct wilson_gauge wilson_gauge;
+typedef struct wilson_batch wilson_batch;
+
+typedef struct {
+    int32_t solver;        /* wilson_solver */
+    int32_t precision;     /* WILSON_FP64: plain FP64 solve; FP32 / FP16 / FP16_L32: mixed
+                              precision, inner solve in that precision, FP64 outer defect
+                              correction (residual, solution and reductions in FP64) */
+    int32_t maxiter;       /* cap on inner iterations summed over all cycles (> 0) */
+    int32_t max_restarts;  /* FP64 path: restarts when the true residual misses tol (<0: 5) */
+    double inner_tol;      /* mixed: relative tolerance of each inner solve (<=0: default
+                              1e-5 for FP32, 1e-2 for FP16) */
+    int32_t use_x0;        /* nonzero: x holds the initial guess on entry */
+    int32_t poll_every;    /* iterations between host convergence polls (<=0: default) */
+} wilson_solve_opts;
+
+typedef struct {
+    int32_t iterations;    /* inner iterations (BiCGStab / CG steps) */
+    int32_t outer_cycles;  /* defect-correction cycles (0 for the FP64 path) */
+    int32_t restarts;
+    int32_t converged;     /* 1 if |b - D x| / |b| < tol in FP64 */
+    double true_residual;  /* |b - D x| / |b| recomputed in FP64 after the solve */
+    double ms;             /* wall time of the call on the host */
+    double hop_launches;   /* parity-hop launches issued */
+} wilson_solve_info;
+
+/* ---------------------------------------------------------------------------------- */
+/* Plain entry points (the library's two-call form).                                  */
+/* ---------------------------------------------------------------------------------- */
+
+/*
+ * Apply the Wilson operator (Eq. (1)) in FP64.
+ *   parity 0 or 1: out = -kappa * H * in on the sites of that parity only (the
+ *                  parity-hop block D_{p,1-p}); sites of the other parity in `out` are
+ *                  not written, and `in` is read only on parity 1-p, so out == in is
+ *                  allowed.
+ *   parity 2:      out = D * in = in - kappa * H * in on every site; out == in is rejected.
+ * out, in: 12*V complex each.  U: 36*V complex (periodic links).  kappa finite.
+ * Uses an internal context on the default stream; synchronous.
+ */
+int wilson_dslash(double *out, const double *in, const double *U, double kappa, const int32_t dims[4],
+                  int32_t parity);
+
+/*
+ * Solve D x = b (Eq. (1)) with FP64 even-odd BiCGStab from x = 0.  Converged when the
+ * FP64 true residual |b - D x| / |b| < tol (recomputed after the iteration stops; the
+ * solve restarts from x if the iterated residual was optimistic).  b = 0 gives x = 0.
+ * Returns WILSON_OK, WILSON_NOT_CONVERGED (x = last iterate) or an error.  Synchronous.
+ */
+int wilson_solve(double *x, const double *b, const double *U, double kappa, const int32_t dims[4], double tol,
+                 int32_t maxiter);
+
+/* ---------------------------------------------------------------------------------- */
+/* Context, resident gauge fields, extended calls.                                    */
+/* ---------------------------------------------------------------------------------- */
+
+/* Create a context bound to the current HIP device and to `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  All work of calls on this context goes to that stream. */
+int wilson_context_create(wilson_ctx **ctx, void *hip_stream);
+int wilson_context_destroy(wilson_ctx *ctx);
+
+/* Upload links (canonical layout, periodic, host or device) and keep them resident in
+ * the library's layout with the antiperiodic sign applied, in each precision requested
+ * by `precisions` (WILSON_GAUGE_* bits; FP64 is always kept).  Links must be SU(3)
+ * (|U_ab| <= 1 is what the FP16 copy relies on). */
+int wilson_gauge_load(wilson_ctx *ctx, wilson_gauge **g, const double *U, const int32_t dims[4],
+                      uint32_t precisions);
+int wilson_gauge_free(wilson_ctx *ctx, wilson_gauge *g);
+/* Device bytes held by a resident gauge field. */
+size_t wilson_gauge_bytes(const wilson_gauge *g);
+
+/*
+ * Dslash on a resident gauge field, for nrhs fields stored back to back (canonical
+ * layout, complex128, host or device).  Semantics of `parity` as wilson_dslash.
+ * `precision` selects the arithmetic: inputs are rounded to it (FP16: per-site scale),
+ * the result is returned as complex128.  nrhs in 1..64.
+ */
+int wilson_dslash_ex(wilson_ctx *ctx, const wilson_gauge *g, double *out, const double *in, double kappa,
+                     int32_t parity, int32_t precision, int32_t nrhs);
+
+/*
+ * Solve D x_k = b_k for k = 0..nrhs-1 on a resident gauge field with per-RHS kappa[k]
+ * and tol[k] (arrays of nrhs doubles, host memory).  opts may be NULL (plain FP64
+ * even-odd BiCGStab).  info, if not NULL, is an array of nrhs records.  The RHS are
+ * solved together: every kernel processes all of them in one launch and each link is
+ * read once per site for all RHS.  Returns the worst status over the RHS.  Synchronous.
+ */
+int wilson_solve_ex(wilson_ctx *ctx, const wilson_gauge *g, double *x, const double *b, int32_t nrhs,
+                    const double *kappa, const double *tol, const wilson_solve_opts *opts,
+                    wilson_solve_info *info);
+
+/* Device bytes wilson_solve_ex would allocate for this lattice, nrhs and options
+ * (workspace only; the resident gauge field is wilson_gauge_bytes). */
+size_t wilson_footprint_bytes(const int32_t dims[4], int32_t nrhs, const wilson_solve_opts *opts);
+
+/* ---------------------------------------------------------------------------------- */
+/* Batched step API for continuous batching (a serving loop keeps one batch per        */
+/* resident gauge field and refills slots as right-hand sides converge).              */
+/* ---------------------------------------------------------------------------------- */
+
+/* A batch of `nslots` independent solves on one resident gauge field; all slots use
+ * opts (solver, precision, inner_tol); kappa and tol are per slot. */
+int wilson_batch_create(wilson_ctx *ctx, const wilson_gauge *g, int32_t nslots, const wilson_solve_opts *opts,
+                        wilson_batch **batch);
+int wilson_batch_destroy(wilson_batch *batch);
+/* Copy b (12*V complex, host or device) into a free slot and start its solve.
+ * WILSON_BUSY if the slot is in use. */
+int wilson_batch_attach(wilson_batch *batch, int32_t slot, const double *b, double kappa, double tol,
+                        int32_t maxiter);
+/* Enqueue up to `iters` iterations for every active slot; returns without waiting. */
+int wilson_batch_step(wilson_batch *batch, int32_t iters);
+/* Per-slot state after the work enqueued so far has completed on the device:
+ * state[k] = 0 free, 1 running, 2 finished (status[k] holds its wilson_status).
+ * Blocks until the device has finished the enqueued steps. */
+int wilson_batch_poll(wilson_batch *batch, int32_t *state, int32_t *status);
+/* Copy a finished slot's solution (12*V complex) to x (host or device) and free the slot.
+ * info may be NULL. */
+int wilson_batch_detach(wilson_batch *batch, int32_t slot, double *x, wilson_solve_info *info);
+
+/* ---------------------------------------------------------------------------------- */
+/* Measurement helpers.                                                                */
+/* ---------------------------------------------------------------------------------- */
+
+/* Kernel classes timed with HIP events when timing is enabled on a context. */
+typedef enum { WILSON_KERNEL_HOP = 0, WILSON_KERNEL_BLAS = 1, WILSON_KERNEL_COUNT = 2 } wilson_kernel_class;
+
+/* Enable (1) / disable (0) event timing of every launch of the timed kernel classes
+ * on the context's stream; enabling clears the accumulators. */
+int wilson_timing_enable(wilson_ctx *ctx, int32_t enable);
+/* Sum of launch durations (ms), launch count and algorithmic bytes of a kernel class
+ * since timing was enabled.  Waits for outstanding timed work. */
+int wilson_timing_read(wilson_ctx *ctx, int32_t kernel_class, double *total_ms, int64_t *launches,
+                       double *bytes);
+
+/* Device-to-device copy of `bytes` bytes with a plain streaming kernel on the context
+ * stream (reference for bandwidth and hardware-counter calibration). */
+int wilson_stream_copy(wilson_ctx *ctx, void *dst, const void *src, size_t bytes);
+
+const char *wilson_strerror(int code);
+const char *wilson_last_error(void);
+/* Library version string. */
+const char *wilson_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WILSON_H */

@@ -1,0 +1,166 @@
+// Internal declarations shared by the host runtime (.cpp) and the kernels (.hip).
+//
+// Data layout in HBM ("parity-split structure of arrays"):
+//   * a lattice site (x,y,z,t) of parity p = (x+y+z+t)&1 has checkerboard index
+//     cb = (x + Lx*(y + Ly*(z + Lz*t))) / 2 in [0, Vh), Vh = V/2;
+//   * a spinor field of one parity is 12 complex "planes" (component c = 3*spin + colour),
+//     plane c holds that component for every cb site: element (c, cb) at [c*stride + cb];
+//     nrhs fields are stacked with rhs stride 12*stride elements.  FP16 fields add one
+//     FP32 scale per site, [rhs*stride + cb];
+//   * links: plane (p, mu, e=3a+b) holds U_mu(x)[a][b] of every parity-p site x:
+//     element [((p*4 + mu)*9 + e)*stride + cb]; the antiperiodic sign is folded into
+//     U_t on the t = Lt-1 slice.
+// One lane processes one site: every plane load of a wavefront is one contiguous,
+// fully coalesced segment.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace wl {
+
+constexpr int kMaxRhs = 64;
+
+enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };
+
+inline size_t real_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+
+struct Geom {
+    int L[4];     // Lx, Ly, Lz, Lt
+    int Lxh;      // Lx / 2
+    int Vh;       // sites per parity
+    int stride;   // plane stride (Vh rounded up to a multiple of 64)
+    int sy, sz, st;  // checkerboard-index strides of +y, +z, +t
+};
+
+Geom make_geom(const int32_t dims[4]);
+
+// A spinor field of one parity (possibly nrhs fields back to back).
+struct Spinor {
+    void *data = nullptr;   // planes: double2 / float2 / _Float16 x2 per complex
+    float *scale = nullptr; // FP16 per-site scales, [rhs][stride]
+    int prec = P64;
+};
+
+inline size_t spinor_plane_bytes(int prec, const Geom &g) { return (size_t)g.stride * 2 * real_bytes(prec); }
+inline size_t spinor_field_bytes(int prec, const Geom &g) {
+    return 12 * spinor_plane_bytes(prec, g) + (prec == P16 ? (size_t)g.stride * 4 : 0);
+}
+
+// Per-right-hand-side Krylov state, resident on the device.  The scalars of the
+// iteration are computed on the device, so the host never has to wait for them.
+enum Phase : int { PH_IDLE = 1, PH_RUN = 2, PH_SCONV = 4, PH_DONE = 8, PH_FAIL = 16 };
+enum FailCode : int { FAIL_NONE = 0, FAIL_BREAKDOWN = 1, FAIL_NONFINITE = 2 };
+
+struct alignas(16) RhsState {
+    double rho_re, rho_im;      // <rhat, r>
+    double alpha_re, alpha_im;
+    double omega_re, omega_im;
+    double beta_re, beta_im;
+    double r2;                  // |r|^2 (iterated residual)
+    double s2;                  // |s|^2
+    double rhat2;               // |rhat|^2
+    double stop2;               // (tol * |b|)^2
+    double zz;                  // CGLS |z|^2
+    double aux;                 // scratch (e.g. a norm returned to the host)
+    int phase;
+    int fail;
+    int iter;
+    int pad;
+};
+
+// Reduction kinds a kernel epilogue can produce (values per block).
+enum RedKind : int { RED_NONE = 0, RED_NORM2 = 1, RED_DOT = 2, RED_TS = 3 };
+__host__ __device__ inline int red_nvals(int kind) { return kind == RED_NONE ? 0 : (kind == RED_NORM2 ? 1 : (kind == RED_DOT ? 2 : 3)); }
+
+// Scalar programs run by the finalize kernel after a reduction.
+enum FinOp : int {
+    FIN_STORE_AUX = 0,  // aux = value 0 (norms for the host)
+    FIN_BICG_INIT,      // r2 = |r|^2, rho = r2, alpha = omega = 1, beta = 0
+    FIN_BICG_ALPHA,     // alpha = rho / <rhat, v>
+    FIN_BICG_S,         // s2 = |s|^2; s-convergence
+    FIN_BICG_OMEGA,     // omega = <t,s> / |t|^2
+    FIN_BICG_RHO,       // r2, rho' -> beta, rho; convergence
+    FIN_CG_R2,          // r2 = |r|^2; convergence at start
+    FIN_CG_ZZ,          // zz = |z|^2 (first)
+    FIN_CG_ALPHA,       // alpha = zz / |w|^2
+    FIN_CG_R,           // r2 after the update; iteration count; convergence
+    FIN_CG_BETA,        // beta = |z'|^2 / zz; zz = |z'|^2
+    FIN_ADD_AUX         // aux += value 0
+};
+
+// Arguments of one parity-hop launch:  out = cH[rhs] * (G5out? g5:1) H (G5in? g5:1) in
+//                                            (+ y) (+ cz * z), on output parity `par`.
+struct HopArgs {
+    Geom g;
+    int par;           // output parity
+    int nrhs;
+    Spinor out, in, y, z, w;  // y, z: same parity as out (optional); w: dot partner
+    const void *gauge; // links of the kernel's precision
+    int gprec;
+    int has_y, has_z, g5in, g5out, nostore;
+    int red;           // RedKind
+    double cz;
+    double cH[kMaxRhs];
+    double *partials;  // [rhs][nvals][pstride]
+    int pstride;       // stride between partial rows (0: the launch's block count)
+    RhsState *state;   // optional: per-rhs phase gate
+    int run_mask;
+};
+
+// Launch configuration chosen by the tuner.
+struct LaunchCfg {
+    int block = 256;
+    int rpt = 1;       // right-hand sides per thread (multi-RHS hop)
+    int xcd = 1;       // XCD-contiguous tile order
+};
+
+// ---- kernel launchers (implemented in the .hip files) ----
+int hop_nblocks(const HopArgs &a, const LaunchCfg &c);
+hipError_t launch_hop(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
+bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c);
+
+// BLAS-1 on one parity, nrhs fields; all take the per-rhs state gate.
+struct BlasArgs {
+    Geom g;
+    int nrhs;
+    Spinor a, b, c, d, e;   // operand roles documented per op
+    Spinor x;               // solution field (may differ in precision)
+    double *partials;       // [rhs][nvals][pstride]
+    int pstride;            // 0: the launch's block count
+    RhsState *state;
+    int run_mask;
+};
+enum BlasOp : int {
+    BL_P_UPDATE = 0,  // a = p: p = r(b) + beta (p - omega v(c))
+    BL_S_UPDATE,      // a = s: s = r(b) - alpha v(c); |s|^2
+    BL_XR_UPDATE,     // x += alpha p(a) + omega s(b); r(c) = s - omega t(d); |r|^2, <rhat(e), r>
+    BL_COPY_NORM,     // a = copy of b; |b|^2
+    BL_CG_XR,         // x += alpha p(a); r(b) -= alpha w(c); |r|^2
+    BL_CG_P,          // p(a) = z(b) + beta p
+    BL_NORM2          // |a|^2
+};
+int blas_nblocks(const Geom &g);
+hipError_t launch_blas(int op, const BlasArgs &a, hipStream_t s);
+hipError_t launch_finalize(int op, const double *partials, int nvals, int nblocks, int nrhs, RhsState *state,
+                           int run_mask, hipStream_t s, RhsState *mirror = nullptr);
+hipError_t launch_zero(const Spinor &f, const Geom &g, int nrhs, hipStream_t s);
+
+// Layout / precision conversion.
+// canonical complex128 [rhs][V][4][3]  <->  parity field of precision f.prec.
+hipError_t launch_to_parity(Spinor f, const double *canon, const Geom &g, int par, int nrhs, double scale,
+                            hipStream_t s);
+hipError_t launch_from_parity(double *canon, Spinor f, const Geom &g, int par, int nrhs, hipStream_t s);
+// dst (prec) = scale * src (FP64 parity field); nrhs fields; scale per rhs from state->aux if use_state.
+hipError_t launch_convert(Spinor dst, Spinor src, const Geom &g, int nrhs, const RhsState *state, int inv_sqrt_aux,
+                          hipStream_t s);
+// x64 += c[rhs] * e (any precision), c from state->aux (sqrt) per rhs.
+hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const RhsState *state, hipStream_t s);
+// Gauge: canonical complex128 links -> parity-split planes in precision prec, t-boundary sign folded.
+hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geom &g, hipStream_t s);
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Checks that canonical input is finite; sets *flag (device int) to 1 otherwise.
+hipError_t launch_check_finite(const double *p, size_t n, int *flag, hipStream_t s);
+
+}  // namespace wl

@@ -1,0 +1,283 @@
+// Parity hop of the Wilson operator (Eq. (1), Sec. 2.1):
+//
+//   out(x) = cH * sum_mu [ (1 - gamma_mu) U_mu(x) in(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag in(x-mu) ]
+//            (+ y(x)) (+ cz * z(x)),   for every site x of the output parity,
+//
+// with optional gamma5 on the input and on the hop result (used for M^dag = g5 M g5),
+// and an optional fused reduction of the result (|out|^2, <w,out>, or <out,y> and |out|^2).
+//
+// One lane owns one output site and `RPT` right-hand sides; every link is loaded once
+// per site and reused for those right-hand sides.  The 4x4 spin structure is applied
+// through spin projection: (1 -/+ gamma_mu) has rank 2, so only a two-spinor "half
+// spinor" h is multiplied by the link (two SU(3) mat-vecs instead of four) and the
+// other two spin rows are rebuilt from it.  In the Dirac basis (gamma_t diagonal)
+// the t projections are (0, 0, 2psi2, 2psi3) forward and (2psi0, 2psi1, 0, 0) backward,
+// so a t-hop reads only two spins of its neighbour.
+//
+// The antiperiodic time boundary is already folded into the t-links (sign on the
+// t = Lt-1 slice), so the kernel is boundary-free apart from periodic wrap-around.
+#include <cstdio>
+
+#include "common.h"
+#include "device.h"
+
+namespace wl {
+
+// --- spin projection / reconstruction tables (Dirac basis) ------------------------
+// forward uses (1 - gamma_mu), backward (1 + gamma_mu).  psi: 4 spins x 3 colours.
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void project(const Cx<R> (&p)[4][3], Cx<R> (&h)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 0) {
+            if constexpr (FWD) { h[0][c] = cadd_i(p[0][c], p[3][c]); h[1][c] = cadd_i(p[1][c], p[2][c]); }
+            else               { h[0][c] = csub_i(p[0][c], p[3][c]); h[1][c] = csub_i(p[1][c], p[2][c]); }
+        } else if constexpr (MU == 1) {
+            if constexpr (FWD) { h[0][c] = cadd(p[0][c], p[3][c]); h[1][c] = csub(p[1][c], p[2][c]); }
+            else               { h[0][c] = csub(p[0][c], p[3][c]); h[1][c] = cadd(p[1][c], p[2][c]); }
+        } else if constexpr (MU == 2) {
+            if constexpr (FWD) { h[0][c] = cadd_i(p[0][c], p[2][c]); h[1][c] = csub_i(p[1][c], p[3][c]); }
+            else               { h[0][c] = csub_i(p[0][c], p[2][c]); h[1][c] = cadd_i(p[1][c], p[3][c]); }
+        } else {
+            if constexpr (FWD) { h[0][c] = cadd(p[2][c], p[2][c]); h[1][c] = cadd(p[3][c], p[3][c]); }
+            else               { h[0][c] = cadd(p[0][c], p[0][c]); h[1][c] = cadd(p[1][c], p[1][c]); }
+        }
+    }
+}
+
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void reconstruct(Cx<R> (&acc)[4][3], const Cx<R> (&u)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 3) {
+            if constexpr (FWD) { acc[2][c] = cadd(acc[2][c], u[0][c]); acc[3][c] = cadd(acc[3][c], u[1][c]); }
+            else               { acc[0][c] = cadd(acc[0][c], u[0][c]); acc[1][c] = cadd(acc[1][c], u[1][c]); }
+        } else {
+            acc[0][c] = cadd(acc[0][c], u[0][c]);
+            acc[1][c] = cadd(acc[1][c], u[1][c]);
+            if constexpr (MU == 0) {
+                if constexpr (FWD) { acc[2][c] = csub_i(acc[2][c], u[1][c]); acc[3][c] = csub_i(acc[3][c], u[0][c]); }
+                else               { acc[2][c] = cadd_i(acc[2][c], u[1][c]); acc[3][c] = cadd_i(acc[3][c], u[0][c]); }
+            } else if constexpr (MU == 1) {
+                if constexpr (FWD) { acc[2][c] = csub(acc[2][c], u[1][c]); acc[3][c] = cadd(acc[3][c], u[0][c]); }
+                else               { acc[2][c] = cadd(acc[2][c], u[1][c]); acc[3][c] = csub(acc[3][c], u[0][c]); }
+            } else {
+                if constexpr (FWD) { acc[2][c] = csub_i(acc[2][c], u[0][c]); acc[3][c] = cadd_i(acc[3][c], u[1][c]); }
+                else               { acc[2][c] = cadd_i(acc[2][c], u[0][c]); acc[3][c] = csub_i(acc[3][c], u[1][c]); }
+            }
+        }
+    }
+}
+
+// Spins of the neighbour a direction needs: t forward reads 2,3; t backward 0,1.
+template <int MU, bool FWD>
+__device__ __forceinline__ constexpr bool spin_needed(int s) {
+    return MU != 3 ? true : (FWD ? s >= 2 : s < 2);
+}
+
+template <int SP, int GP, int RPT, int MU, bool FWD>
+__device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
+                                        int r0, int nbr, int link_par, int link_site) {
+    using R = real_t<SP>;
+    const int stride = a.g.stride;
+    // link U_mu(x) (forward, at the output site) or U_mu(x - mu) (backward, at the neighbour)
+    Cx<R> U[3][3];
+    const size_t lbase = (size_t)((link_par * 4 + MU) * 9) * stride + link_site;
+#pragma unroll
+    for (int e = 0; e < 9; e++) U[e / 3][e % 3] = ld_c_nt<GP, R>(a.gauge, lbase + (size_t)e * stride);
+
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        if (!act[r]) continue;
+        const size_t sbase = (size_t)(r0 + r) * 12 * stride + nbr;
+        Cx<R> p[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            if (!spin_needed<MU, FWD>(s)) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) p[s][c] = {R(0), R(0)};
+                continue;
+            }
+            // gamma5 on the input: (g5 psi)_s = -psi_{s^2}
+            const int src = a.g5in ? (s ^ 2) : s;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                Cx<R> v = ld_c<SP, R>(a.in.data, sbase + (size_t)(src * 3 + c) * stride);
+                p[s][c] = a.g5in ? Cx<R>{-v.re, -v.im} : v;
+            }
+        }
+        Cx<R> h[2][3];
+        project<MU, FWD, R>(p, h);
+        if constexpr (SP == P16) {
+            const R sc = (R)a.in.scale[(size_t)(r0 + r) * stride + nbr];
+#pragma unroll
+            for (int k = 0; k < 2; k++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) h[k][c] = cscale(h[k][c], sc);
+        }
+        Cx<R> u[2][3];
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int a_ = 0; a_ < 3; a_++) {
+                Cx<R> t = {R(0), R(0)};
+#pragma unroll
+                for (int b_ = 0; b_ < 3; b_++) {
+                    if constexpr (FWD) t = cfma(t, U[a_][b_], h[k][b_]);       // U h
+                    else               t = cfma_conj(t, U[b_][a_], h[k][b_]);  // U^dag h
+                }
+                u[k][a_] = t;
+            }
+        reconstruct<MU, FWD, R>(acc[r], u);
+    }
+}
+
+template <int SP, int GP, int RPT>
+__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a, int xcd_remap) {
+    using R = real_t<SP>;
+    const Geom &g = a.g;
+    const int r0 = blockIdx.y * RPT;
+    bool act[RPT];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        act[r] = (r0 + r < a.nrhs) && (a.state == nullptr || (a.state[r0 + r].phase & a.run_mask));
+        any |= act[r];
+    }
+    if (!any) return;  // uniform over the block
+
+    const int tile = xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int i_raw = tile * blockDim.x + threadIdx.x;
+    const bool valid = i_raw < g.Vh;
+    const int i = valid ? i_raw : g.Vh - 1;
+    const int par = a.par, opar = 1 - par;
+    const SiteXY c = cb_coords(g, i, par);
+    const int row = i - c.xh;
+    const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
+    const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
+    const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
+    const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
+    const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
+    const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
+    const int tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
+    const int tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+
+    Cx<R> acc[RPT][4][3];
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc[r][s][k] = {R(0), R(0)};
+
+    hop_dir<SP, GP, RPT, 0, true>(acc, a, act, r0, xp, par, i);
+    hop_dir<SP, GP, RPT, 0, false>(acc, a, act, r0, xm, opar, xm);
+    hop_dir<SP, GP, RPT, 1, true>(acc, a, act, r0, yp, par, i);
+    hop_dir<SP, GP, RPT, 1, false>(acc, a, act, r0, ym, opar, ym);
+    hop_dir<SP, GP, RPT, 2, true>(acc, a, act, r0, zp, par, i);
+    hop_dir<SP, GP, RPT, 2, false>(acc, a, act, r0, zm, opar, zm);
+    hop_dir<SP, GP, RPT, 3, true>(acc, a, act, r0, tp, par, i);
+    hop_dir<SP, GP, RPT, 3, false>(acc, a, act, r0, tm, opar, tm);
+
+    const int nv = red_nvals(a.red);
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        if (!act[r]) continue;
+        const int rhs = r0 + r;
+        const R cH = (R)a.cH[rhs];
+        Cx<R> o[12];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // gamma5 on the hop result: (g5 v)_s = -v_{s^2}
+                Cx<R> v = a.g5out ? Cx<R>{-acc[r][s ^ 2][k].re, -acc[r][s ^ 2][k].im} : acc[r][s][k];
+                o[s * 3 + k] = cscale(v, cH);
+            }
+        Cx<R> yv[12];
+        if (a.has_y) {
+            load_site<SP, R>(yv, a.y, g.stride, rhs, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], yv[k]);
+        }
+        if (a.has_z) {
+            Cx<R> zv[12];
+            load_site<SP, R>(zv, a.z, g.stride, rhs, i);
+            const R cz = (R)a.cz;
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
+        }
+        if (valid && !a.nostore) store_site<SP, R>(a.out, g.stride, rhs, i, o);
+        if (nv == 0) continue;
+        const int ps = a.pstride ? a.pstride : (int)gridDim.x;
+        double *dst = a.partials + (size_t)rhs * nv * ps + tile;
+        if (a.red == RED_NORM2) {
+            double v[1] = {0.0};
+            if (valid)
+                for (int k = 0; k < 12; k++) v[0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+            block_reduce_to<1>(v, dst, ps);
+        } else if (a.red == RED_DOT) {
+            double v[2] = {0.0, 0.0};
+            if (valid) {
+                Cx<R> wv[12];
+                load_site<SP, R>(wv, a.w, g.stride, rhs, i);
+                for (int k = 0; k < 12; k++) {  // <w, o> = sum conj(w) o
+                    v[0] += (double)wv[k].re * o[k].re + (double)wv[k].im * o[k].im;
+                    v[1] += (double)wv[k].re * o[k].im - (double)wv[k].im * o[k].re;
+                }
+            }
+            block_reduce_to<2>(v, dst, ps);
+        } else {
+            double v[3] = {0.0, 0.0, 0.0};
+            if (valid)
+                for (int k = 0; k < 12; k++) {  // <o, y> and |o|^2
+                    v[0] += (double)o[k].re * yv[k].re + (double)o[k].im * yv[k].im;
+                    v[1] += (double)o[k].re * yv[k].im - (double)o[k].im * yv[k].re;
+                    v[2] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+                }
+            block_reduce_to<3>(v, dst, ps);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
+    if (c.block != 64 && c.block != 128 && c.block != 256) return false;
+    if (c.rpt < 1 || c.rpt > 4) return false;
+    if (a.nrhs % c.rpt != 0) return false;
+    if (a.in.prec == P64 && c.rpt > 2) return false;
+    return true;
+}
+
+int hop_nblocks(const HopArgs &a, const LaunchCfg &c) { return (a.g.Vh + c.block - 1) / c.block; }
+
+template <int SP, int GP>
+static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    dim3 grid(hop_nblocks(a, c), a.nrhs / c.rpt);
+    dim3 block(c.block);
+    const int remap = c.xcd;
+    switch (c.rpt) {
+        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1>), grid, block, 0, s, a, remap); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2>), grid, block, 0, s, a, remap); break;
+        case 3:
+            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 3>), grid, block, 0, s, a, remap);
+            break;
+        case 4:
+            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 4>), grid, block, 0, s, a, remap);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hop(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    if (!hop_cfg_valid(a, c)) return hipErrorInvalidValue;
+    const int sp = a.in.prec, gp = a.gprec;
+    if (sp == P64 && gp == P64) return launch_hop_t<P64, P64>(a, c, s);
+    if (sp == P32 && gp == P32) return launch_hop_t<P32, P32>(a, c, s);
+    if (sp == P16 && gp == P16) return launch_hop_t<P16, P16>(a, c, s);
+    if (sp == P16 && gp == P32) return launch_hop_t<P16, P32>(a, c, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wl

@@ -1,0 +1,265 @@
+// Host runtime: geometry, device memory, pointer classification, event timing and the
+// launch-configuration autotuner.
+#include "runtime.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+namespace wl {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+const std::string &last_error() { return g_last_error; }
+
+void hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    std::ostringstream os;
+    os << "HIP error " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ") in " << what << " at " << file
+       << ":" << line;
+    throw Error(e == hipErrorOutOfMemory ? WILSON_OUT_OF_MEMORY : WILSON_DEVICE_ERROR, os.str());
+}
+
+Geom make_geom(const int32_t dims[4]) {
+    Geom g;
+    for (int k = 0; k < 4; k++) g.L[k] = dims[k];
+    g.Lxh = dims[0] / 2;
+    const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    g.Vh = (int)(V / 2);
+    g.stride = (int)(((V / 2) + 63) / 64 * 64);
+    g.sy = g.Lxh;
+    g.sz = g.Lxh * dims[1];
+    g.st = g.Lxh * dims[1] * dims[2];
+    return g;
+}
+
+void DevBuf::alloc(size_t bytes) {
+    release();
+    if (bytes == 0) return;
+    hipError_t e = hipMalloc(&p_, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p_ = nullptr;
+        throw Error(WILSON_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    n_ = bytes;
+}
+
+void DevBuf::release() {
+    if (p_) (void)hipFree(p_);
+    p_ = nullptr;
+    n_ = 0;
+}
+
+void PinnedBuf::alloc(size_t bytes) {
+    if (h_) (void)hipHostFree(h_);
+    h_ = d_ = nullptr;
+    n_ = 0;
+    WL_HIP(hipHostMalloc(&h_, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+    WL_HIP(hipHostGetDevicePointer(&d_, h_, 0));
+    std::memset(h_, 0, bytes);
+    n_ = bytes;
+}
+
+PinnedBuf::~PinnedBuf() {
+    if (h_) (void)hipHostFree(h_);
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+size_t partials_doubles(const Geom &g, int nrhs) {
+    const size_t nb = (size_t)(g.Vh + 63) / 64;  // smallest block size the tuner uses
+    return (size_t)nrhs * 3 * nb * 2 + 64;       // x2: both parities in one row
+}
+
+double hop_bytes(const HopArgs &a) {
+    const double sb = 24.0 * real_bytes(a.in.prec) + (a.in.prec == P16 ? 4.0 : 0.0);
+    const double lb = 8.0 * 18.0 * real_bytes(a.gprec);
+    double per_rhs = sb;                 // input field, each site once
+    if (!a.nostore) per_rhs += sb;       // output
+    if (a.has_y) per_rhs += sb;
+    if (a.has_z) per_rhs += sb;
+    if (a.red == RED_DOT) per_rhs += sb;  // dot partner
+    return (double)a.g.Vh * (lb + a.nrhs * per_rhs);
+}
+
+}  // namespace wl
+
+using namespace wl;
+
+hipEvent_t wilson_ctx::get_event() {
+    if (!event_pool.empty()) {
+        hipEvent_t e = event_pool.back();
+        event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    WL_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void wilson_ctx::drain_timing() {
+    for (auto &p : pending) {
+        WL_HIP(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        WL_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        t_ms[p.cls] += ms;
+        launches[p.cls] += 1;
+        t_bytes[p.cls] += p.bytes;
+        event_pool.push_back(p.a);
+        event_pool.push_back(p.b);
+    }
+    pending.clear();
+}
+
+void *wilson_ctx::stage(DevBuf &b, size_t bytes) {
+    if (b.size() < bytes) {
+        WL_HIP(hipStreamSynchronize(stream));
+        b.alloc(bytes);
+    }
+    return b.get();
+}
+
+void wilson_ctx::load_tune_cache() {
+    tune_loaded = true;
+    const char *env = std::getenv("WILSON_TUNE");
+    if (env && std::strcmp(env, "0") == 0) tune_enabled = false;
+    const char *path = std::getenv("WILSON_TUNE_CACHE");
+    if (!path || !*path) return;
+    tune_path = path;
+    std::ifstream in(tune_path);
+    std::string line;
+    // one JSON object per line: {"key": "...", "block": B, "rpt": R, "xcd": X, "ms": T}
+    while (std::getline(in, line)) {
+        const size_t k0 = line.find("\"key\": \"");
+        if (k0 == std::string::npos) continue;
+        const size_t k1 = line.find('"', k0 + 8);
+        if (k1 == std::string::npos) continue;
+        const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
+        LaunchCfg c;
+        if (std::sscanf(line.c_str() + k1, "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d", &c.block, &c.rpt, &c.xcd) == 3)
+            tuned[key] = c;
+    }
+}
+
+void wilson_ctx::save_tune_entry(const std::string &key, const LaunchCfg &c, double ms) {
+    if (tune_path.empty()) return;
+    std::ofstream out(tune_path, std::ios::app);
+    out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
+        << ", \"ms\": " << ms << "}\n";
+}
+
+namespace wl {
+
+static std::string hop_key(const HopArgs &a) {
+    std::ostringstream os;
+    os << "hop sp=" << a.in.prec << " gp=" << a.gprec << " nrhs=" << a.nrhs << " red=" << a.red << " y=" << a.has_y
+       << " dims=" << a.g.L[0] << "x" << a.g.L[1] << "x" << a.g.L[2] << "x" << a.g.L[3];
+    return os.str();
+}
+
+static LaunchCfg default_cfg(const HopArgs &a) {
+    LaunchCfg c;
+    c.block = 256;
+    c.xcd = 1;
+    const int maxr = a.in.prec == P64 ? 2 : 4;
+    for (int r = maxr; r >= 1; r--)
+        if (a.nrhs % r == 0) { c.rpt = r; break; }
+    return c;
+}
+
+// Time each candidate configuration on the live arguments (the hop is a pure function of
+// its inputs, so repeated launches are harmless) and keep the fastest.
+static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
+    std::vector<LaunchCfg> cands;
+    for (int block : {64, 128, 256})
+        for (int rpt : {1, 2, 3, 4})
+            for (int xcd : {0, 1}) {
+                LaunchCfg c;
+                c.block = block;
+                c.rpt = rpt;
+                c.xcd = xcd;
+                if (hop_cfg_valid(a, c)) cands.push_back(c);
+            }
+    hipEvent_t e0, e1;
+    WL_HIP(hipEventCreate(&e0));
+    WL_HIP(hipEventCreate(&e1));
+    LaunchCfg best = default_cfg(a);
+    double bms = 1e30;
+    const int reps = a.g.Vh >= (1 << 18) ? 3 : 10;
+    for (const auto &c : cands) {
+        WL_HIP(launch_hop(a, c, ctx->stream));  // warm-up
+        WL_HIP(hipEventRecord(e0, ctx->stream));
+        for (int r = 0; r < reps; r++) WL_HIP(launch_hop(a, c, ctx->stream));
+        WL_HIP(hipEventRecord(e1, ctx->stream));
+        WL_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / reps;
+        if (per < bms) {
+            bms = per;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best_ms = bms;
+    return best;
+}
+
+int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
+    if (a.nrhs < 1 || a.nrhs > kMaxRhs) throw Error(WILSON_INVALID_ARG, "nrhs out of range");
+    if (a.out.data == a.in.data || (a.has_y && a.out.data == a.y.data) || (a.has_z && a.out.data == a.z.data))
+        throw Error(WILSON_INVALID_ARG, "hop output aliases an input");
+    if (!ctx->tune_loaded) ctx->load_tune_cache();
+    const std::string key = hop_key(a);
+    LaunchCfg cfg;
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end() && hop_cfg_valid(a, it->second)) {
+        cfg = it->second;
+    } else if (ctx->tune_enabled && a.g.Vh >= 4096) {
+        double ms = 0;
+        cfg = tune_hop(ctx, a, &ms);
+        ctx->tuned[key] = cfg;
+        ctx->save_tune_entry(key, cfg, ms);
+    } else {
+        cfg = default_cfg(a);
+        ctx->tuned[key] = cfg;
+    }
+    ctx->hop_launch_count++;
+    if (ctx->timing) {
+        hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
+        WL_HIP(hipEventRecord(e0, ctx->stream));
+        WL_HIP(launch_hop(a, cfg, ctx->stream));
+        WL_HIP(hipEventRecord(e1, ctx->stream));
+        ctx->pending.push_back({e0, e1, WILSON_KERNEL_HOP, algorithmic_bytes});
+    } else {
+        WL_HIP(launch_hop(a, cfg, ctx->stream));
+    }
+    return hop_nblocks(a, cfg);
+}
+
+void blas(wilson_ctx *ctx, int op, BlasArgs &a, double algorithmic_bytes) {
+    if (ctx->timing) {
+        hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
+        WL_HIP(hipEventRecord(e0, ctx->stream));
+        WL_HIP(launch_blas(op, a, ctx->stream));
+        WL_HIP(hipEventRecord(e1, ctx->stream));
+        ctx->pending.push_back({e0, e1, WILSON_KERNEL_BLAS, algorithmic_bytes});
+    } else {
+        WL_HIP(launch_blas(op, a, ctx->stream));
+    }
+}
+
+}  // namespace wl

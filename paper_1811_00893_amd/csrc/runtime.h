@@ -1,0 +1,143 @@
+// Host runtime: contexts, resident gauge fields, device memory, event timing, the
+// launch-configuration autotuner and error plumbing.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "wilson.h"
+
+namespace wl {
+
+// Internal error carrying a wilson_status; converted to a return code at the ABI.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &m);
+const std::string &last_error();
+[[noreturn]] void hip_fail(hipError_t e, const char *what, const char *file, int line);
+#define WL_HIP(x)                                                 \
+    do {                                                          \
+        hipError_t _e = (x);                                      \
+        if (_e != hipSuccess) ::wl::hip_fail(_e, #x, __FILE__, __LINE__); \
+    } while (0)
+#define WL_CHECK_ARG(cond, msg)                                   \
+    do {                                                          \
+        if (!(cond)) throw ::wl::Error(WILSON_INVALID_ARG, msg);  \
+    } while (0)
+
+// Owning device allocation.
+class DevBuf {
+   public:
+    DevBuf() = default;
+    explicit DevBuf(size_t bytes) { alloc(bytes); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+        return *this;
+    }
+    void alloc(size_t bytes);
+    void release();
+    void *get() const { return p_; }
+    size_t size() const { return n_; }
+    template <typename T>
+    T *as() const { return reinterpret_cast<T *>(p_); }
+
+   private:
+    void *p_ = nullptr;
+    size_t n_ = 0;
+};
+
+// Owning pinned host allocation, mapped into the device address space.
+class PinnedBuf {
+   public:
+    PinnedBuf() = default;
+    ~PinnedBuf();
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    void alloc(size_t bytes);
+    void *host() const { return h_; }
+    void *dev() const { return d_; }
+    size_t size() const { return n_; }
+
+   private:
+    void *h_ = nullptr;
+    void *d_ = nullptr;
+    size_t n_ = 0;
+};
+
+bool is_device_ptr(const void *p);
+
+}  // namespace wl
+
+struct wilson_gauge {
+    wl::Geom g;
+    int32_t dims[4];
+    wl::DevBuf U[3];  // per wl::Prec
+    size_t bytes() const { return U[0].size() + U[1].size() + U[2].size(); }
+    const void *links(int prec) const { return U[prec].get(); }
+};
+
+struct wilson_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    // ---- event timing ----
+    bool timing = false;
+    struct Pending {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double t_ms[WILSON_KERNEL_COUNT] = {0, 0};
+    int64_t launches[WILSON_KERNEL_COUNT] = {0, 0};
+    double t_bytes[WILSON_KERNEL_COUNT] = {0, 0};
+    int64_t hop_launch_count = 0;  // always counted
+
+    hipEvent_t get_event();
+    void drain_timing();  // resolves pending event pairs (waits for them)
+
+    // ---- autotuner ----
+    std::map<std::string, wl::LaunchCfg> tuned;
+    bool tune_enabled = true;
+    bool tune_loaded = false;
+    std::string tune_path;
+    void load_tune_cache();
+    void save_tune_entry(const std::string &key, const wl::LaunchCfg &c, double ms);
+
+    // ---- scratch ----
+    wl::DevBuf stage_in, stage_out;  // canonical staging for host pointers
+    wl::DevBuf flag;                 // device int for finiteness checks
+    wl::PinnedBuf pinned;            // small host mirror
+    // cached workspaces of the last dslash / solve shape (reused across calls)
+    std::shared_ptr<void> dslash_ws, solve_ws;
+    std::string dslash_key, solve_key;
+    void *stage(wl::DevBuf &b, size_t bytes);
+};
+
+namespace wl {
+
+// Launch a parity hop with the tuned configuration, timed if timing is on.
+// algorithmic_bytes is the per-launch byte count used for achieved-bandwidth figures.
+// Returns the number of blocks launched (the row length of the partials it wrote).
+int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes);
+// Launch a BLAS kernel (timed as class BLAS).
+void blas(wilson_ctx *ctx, int op, BlasArgs &a, double algorithmic_bytes);
+// Size of a partials buffer (doubles) that any hop or BLAS launch on g with nrhs can use.
+size_t partials_doubles(const Geom &g, int nrhs);
+// Algorithmic bytes of one hop launch (per output site: 8 links + input + output (+ y, z, w)).
+double hop_bytes(const HopArgs &a);
+
+}  // namespace wl
