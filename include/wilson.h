@@ -7,13 +7,12 @@
  *                                                + (1 + gamma_mu) U_mu(x-mu)^dag delta_{x-mu,y} ]
  *          = 1 - kappa * H,
  *
- * acting on complex fields with 4 spin x 3 colour components per site (Sec. 2, "The
- * fermion field ... 12 degrees of freedom on each site"), with SU(3) links U_mu(x) on
- * the 4 directions.  The linear system D x = b is solved with a Krylov method
- * (BiCGStab, Sec. 2 "We employ the BiCGStab algorithm"), here on the even-odd
- * preconditioned Schur system, with CG on the normal equations as a second method and
- * a mixed-precision (FP32 / FP16 inner, FP64 outer) variant (Sec. 2: a single-precision
- * inner solver of a mixed-precision solver governs the cost of the whole solve).
+ * acting on complex fields with 4 spin x 3 colour components per site and SU(3) links
+ * U_mu(x) on the 4 directions (Sec. 2).  The linear system D x = b is solved with
+ * BiCGStab, the Krylov method of Sec. 2, here on the even-odd preconditioned Schur
+ * system, with CG on the normal equations as a second method, and in a mixed-precision
+ * variant (FP32 / FP16 inner solve, FP64 outer correction); Sec. 2 motivates the latter:
+ * in practice the single-precision inner solve dominates the cost of the whole solve.
  *
  * CONVENTIONS (all entry points)
  *   dims  = {Lx, Ly, Lz, Lt}; every extent even and >= 2.  V = Lx*Ly*Lz*Lt.
@@ -221,6 +220,9 @@ int wilson_timing_read(wilson_ctx *ctx, int32_t kernel_class, double *total_ms, 
 /* Device-to-device copy of `bytes` bytes with a plain streaming kernel on the context
  * stream (reference for bandwidth and hardware-counter calibration). */
 int wilson_stream_copy(wilson_ctx *ctx, void *dst, const void *src, size_t bytes);
+/* Read `bytes` bytes of device memory with a plain streaming kernel on the context stream
+ * (read-only bandwidth reference; the data is not modified). */
+int wilson_stream_read(wilson_ctx *ctx, const void *src, size_t bytes);
 
 const char *wilson_strerror(int code);
 const char *wilson_last_error(void);

@@ -38,7 +38,7 @@ EXPORTS = [
     "wilson_gauge_free", "wilson_gauge_bytes", "wilson_dslash_ex", "wilson_solve_ex", "wilson_footprint_bytes",
     "wilson_batch_create", "wilson_batch_destroy", "wilson_batch_attach", "wilson_batch_step", "wilson_batch_poll",
     "wilson_batch_detach", "wilson_timing_enable", "wilson_timing_read", "wilson_stream_copy", "wilson_strerror",
-    "wilson_last_error", "wilson_version",
+    "wilson_last_error", "wilson_version", "wilson_stream_read",
 ]
 
 
@@ -82,6 +82,7 @@ _SIGS = {
     "wilson_timing_read": (_i32, [_vp, _i32, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(_d)]),
     "wilson_stream_copy": (_i32, [_vp, _vp, _vp, ctypes.c_size_t]),
+    "wilson_stream_read": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "wilson_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "wilson_last_error": (ctypes.c_char_p, []),
     "wilson_version": (ctypes.c_char_p, []),
@@ -287,3 +288,7 @@ def wilson_timing_read(ctx, kernel_class=WILSON_KERNEL_HOP):
 
 def wilson_stream_copy(ctx, dst, src, nbytes):
     return check(lib().wilson_stream_copy(ctx, _ptr(dst), _ptr(src), int(nbytes)), "wilson_stream_copy")
+
+
+def wilson_stream_read(ctx, src, nbytes):
+    return check(lib().wilson_stream_read(ctx, _ptr(src), int(nbytes)), "wilson_stream_read")

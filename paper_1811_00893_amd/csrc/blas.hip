@@ -190,10 +190,21 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, i
         __shared__ double tot[3];
         double v[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < nv; k++) {
+            // 8 independent accumulators keep 8 loads in flight per thread; the grouping
+            // is fixed, so the sum is the same on every run
             const double *p = partials + ((size_t)rhs * nv + k) * nblocks;
-            double acc = 0.0;
-            for (int j = threadIdx.x; j < nblocks; j += blockDim.x) acc += p[j];
-            v[k] = acc;
+            double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const int step = blockDim.x * 8;
+            int j0 = threadIdx.x;
+            for (; j0 + 7 * (int)blockDim.x < nblocks; j0 += step) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) acc[u] += p[j0 + u * blockDim.x];
+            }
+            for (int u = 0; u < 8; u++) {
+                const int j = j0 + u * blockDim.x;
+                if (j < nblocks) acc[u] += p[j];
+            }
+            v[k] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         }
         block_reduce_to<3>(v, tot, 1);
         if (threadIdx.x == 0) fin_op<OP>(st, tot[0], tot[1], tot[2]);

@@ -1,6 +1,7 @@
 // extern "C" entry points declared in include/wilson.h.  Arguments are validated before
 // any device work; no C++ exception crosses this boundary.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -74,12 +75,28 @@ wilson_gauge *load_gauge(wilson_ctx *ctx, const double *U, const int32_t *dims, 
         const size_t links = (size_t)72 * dims[0] * dims[1] * dims[2] * dims[3];  // doubles
         DevBuf tmp;
         Staged su(ctx, tmp, U, links * sizeof(double), true);
+        // Two-row storage needs exact SU(3) links (to well below the FP64 parity tolerance);
+        // anything else is kept in full.  WILSON_RECON=18 forces full storage.
+        int recon = 12;
+        const char *env = std::getenv("WILSON_RECON");
+        if (env && std::strcmp(env, "18") == 0) recon = 18;
+        if (recon == 12) {
+            if (ctx->flag.size() < sizeof(int)) ctx->flag.alloc(256);
+            static const int zero = 0;
+            WL_HIP(hipMemcpyAsync(ctx->flag.get(), &zero, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+            WL_HIP(launch_su3_check(su.dev, links / 18, 1e-13, ctx->flag.as<int>(), ctx->stream));
+            int bad = 0;
+            WL_HIP(hipMemcpyAsync(&bad, ctx->flag.get(), sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            WL_HIP(hipStreamSynchronize(ctx->stream));
+            if (bad) recon = 18;
+        }
+        G->recon = recon;
         for (int prec = 0; prec < 3; prec++) {
             const bool want = prec == P64 || (prec == P32 && (precisions & WILSON_GAUGE_FP32)) ||
                               (prec == P16 && (precisions & WILSON_GAUGE_FP16));
             if (!want) continue;
-            G->U[prec].alloc((size_t)2 * 4 * 9 * G->g.stride * 2 * real_bytes(prec));
-            WL_HIP(launch_gauge_pack(G->U[prec].get(), prec, su.dev, G->g, ctx->stream));
+            G->U[prec].alloc(gauge_bytes(prec, recon, G->g));
+            WL_HIP(launch_gauge_pack(G->U[prec].get(), prec, su.dev, G->g, recon, ctx->stream));
         }
         WL_HIP(hipStreamSynchronize(ctx->stream));
     } catch (...) {
@@ -432,6 +449,19 @@ int wilson_stream_copy(wilson_ctx *ctx, void *dst, const void *src, size_t bytes
     WL_CHECK_ARG(ctx && dst && src, "NULL argument");
     WL_CHECK_ARG(is_device_ptr(dst) && is_device_ptr(src), "stream copy needs device pointers");
     WL_HIP(launch_stream_copy(dst, src, bytes, ctx->stream));
+    return WILSON_OK;
+    API_END
+}
+
+int wilson_stream_read(wilson_ctx *ctx, const void *src, size_t bytes) {
+    API_BEGIN
+    WL_CHECK_ARG(ctx && src, "NULL argument");
+    WL_CHECK_ARG(is_device_ptr(src), "stream read needs a device pointer");
+    if (ctx->flag.size() < 8192 * sizeof(unsigned)) {
+        WL_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->flag.alloc(8192 * sizeof(unsigned));
+    }
+    WL_HIP(launch_stream_read(src, bytes, ctx->flag.as<unsigned>(), ctx->stream));
     return WILSON_OK;
     API_END
 }

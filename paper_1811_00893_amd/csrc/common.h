@@ -99,6 +99,7 @@ struct HopArgs {
     Spinor out, in, y, z, w;  // y, z: same parity as out (optional); w: dot partner
     const void *gauge; // links of the kernel's precision
     int gprec;
+    int recon;         // 18: full links, sign folded; 12: two rows, third rebuilt, t-boundary sign applied here
     int has_y, has_z, g5in, g5out, nostore;
     int red;           // RedKind
     double cz;
@@ -114,6 +115,7 @@ struct LaunchCfg {
     int block = 256;
     int rpt = 1;       // right-hand sides per thread (multi-RHS hop)
     int xcd = 1;       // XCD-contiguous tile order
+    int zblk = 0;      // >0: visit (z,t) planes in blocks of zblk z-values, t inner (divides Lz)
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----
@@ -157,9 +159,18 @@ hipError_t launch_convert(Spinor dst, Spinor src, const Geom &g, int nrhs, const
                           hipStream_t s);
 // x64 += c[rhs] * e (any precision), c from state->aux (sqrt) per rhs.
 hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const RhsState *state, hipStream_t s);
-// Gauge: canonical complex128 links -> parity-split planes in precision prec, t-boundary sign folded.
-hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geom &g, hipStream_t s);
+// Gauge: canonical complex128 links -> parity-split planes in precision prec.
+// recon 18: all 9 entries, t-boundary sign folded in; recon 12: rows 0 and 1 only, no sign.
+hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geom &g, int recon, hipStream_t s);
+// Sets *flag (device int) to 1 if any canonical link deviates from SU(3) by more than tol
+// (max |U U^dag - 1|, |det U - 1|).
+hipError_t launch_su3_check(const double *canon, size_t nlinks, double tol, int *flag, hipStream_t s);
+inline size_t gauge_bytes(int prec, int recon, const Geom &g) {
+    return (size_t)2 * 4 * (recon == 12 ? 6 : 9) * g.stride * 2 * real_bytes(prec);
+}
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Read-only bandwidth probe; sink needs 8192 unsigned words.
+hipError_t launch_stream_read(const void *src, size_t bytes, unsigned *sink, hipStream_t s);
 // Checks that canonical input is finite; sets *flag (device int) to 1 otherwise.
 hipError_t launch_check_finite(const double *p, size_t n, int *flag, hipStream_t s);
 

@@ -100,12 +100,63 @@ __device__ __forceinline__ void st_c(void *base, size_t idx, Cx<R> v) {
     }
 }
 
+// ---- plane addressing: a wave-uniform plane base plus one 32-bit per-lane byte offset,
+// so that every plane load of a site shares the same offset register and the base
+// stays in scalar registers ----
+template <int P>
+struct Elem {
+    static constexpr unsigned bytes = P == P64 ? 16u : (P == P32 ? 8u : 4u);
+};
+template <int P>
+__device__ __forceinline__ const char *plane_ptr(const void *base, int plane, int stride) {
+    return static_cast<const char *>(base) + (size_t)plane * stride * Elem<P>::bytes;
+}
+template <int P, typename R>
+__device__ __forceinline__ Cx<R> ld_p(const char *plane, unsigned off) {
+    if constexpr (P == P64) {
+        double2 v = *reinterpret_cast<const double2 *>(plane + off);
+        return {(R)v.x, (R)v.y};
+    } else if constexpr (P == P32) {
+        float2 v = *reinterpret_cast<const float2 *>(plane + off);
+        return {(R)v.x, (R)v.y};
+    } else {
+        half2_t v = *reinterpret_cast<const half2_t *>(plane + off);
+        return {(R)(float)v.x, (R)(float)v.y};
+    }
+}
+template <int P, typename R>
+__device__ __forceinline__ Cx<R> ld_p_nt(const char *plane, unsigned off) {
+    if constexpr (P == P64) {
+        dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(plane + off));
+        return {(R)v.x, (R)v.y};
+    } else if constexpr (P == P32) {
+        fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2 *>(plane + off));
+        return {(R)v.x, (R)v.y};
+    } else {
+        half2_t v = __builtin_nontemporal_load(reinterpret_cast<const half2_t *>(plane + off));
+        return {(R)(float)v.x, (R)(float)v.y};
+    }
+}
+template <int P, typename R>
+__device__ __forceinline__ void st_p(char *plane, unsigned off, Cx<R> v) {
+    if constexpr (P == P64) {
+        *reinterpret_cast<double2 *>(plane + off) = make_double2((double)v.re, (double)v.im);
+    } else if constexpr (P == P32) {
+        *reinterpret_cast<float2 *>(plane + off) = make_float2((float)v.re, (float)v.im);
+    } else {
+        half2_t h;
+        h.x = (_Float16)(float)v.re;
+        h.y = (_Float16)(float)v.im;
+        *reinterpret_cast<half2_t *>(plane + off) = h;
+    }
+}
+
 // Full site (12 complex) of rhs `r` of a parity field; FP16 values are rescaled.
 template <int P, typename R>
 __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int stride, int r, int i) {
-    const size_t base = (size_t)r * 12 * stride + i;
+    const unsigned off = (unsigned)i * Elem<P>::bytes;
 #pragma unroll
-    for (int c = 0; c < 12; c++) v[c] = ld_c<P, R>(f.data, base + (size_t)c * stride);
+    for (int c = 0; c < 12; c++) v[c] = ld_p<P, R>(plane_ptr<P>(f.data, r * 12 + c, stride), off);
     if constexpr (P == P16) {
         const R s = (R)f.scale[(size_t)r * stride + i];
 #pragma unroll
@@ -116,7 +167,7 @@ __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int s
 // FP16 encoding of a site: s = max |component| (FP32), h = fp16_rne(fp32(v / s)), s = 0 -> zeros.
 template <int P, typename R>
 __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, int i, const Cx<R> (&v)[12]) {
-    const size_t base = (size_t)r * 12 * stride + i;
+    const unsigned off = (unsigned)i * Elem<P>::bytes;
     if constexpr (P == P16) {
         float vf[24];
 #pragma unroll
@@ -133,12 +184,12 @@ __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, i
             half2_t h;
             h.x = (_Float16)(s > 0.f ? vf[2 * c] / sd : 0.f);
             h.y = (_Float16)(s > 0.f ? vf[2 * c + 1] / sd : 0.f);
-            reinterpret_cast<half2_t *>(f.data)[base + (size_t)c * stride] = h;
+            *reinterpret_cast<half2_t *>(const_cast<char *>(plane_ptr<P>(f.data, r * 12 + c, stride)) + off) = h;
         }
         f.scale[(size_t)r * stride + i] = s;
     } else {
 #pragma unroll
-        for (int c = 0; c < 12; c++) st_c<P, R>(f.data, base + (size_t)c * stride, v[c]);
+        for (int c = 0; c < 12; c++) st_p<P, R>(const_cast<char *>(plane_ptr<P>(f.data, r * 12 + c, stride)), off, v[c]);
     }
 }
 
@@ -184,6 +235,22 @@ __device__ __forceinline__ SiteXY cb_coords(const Geom &g, int i, int par) {
     c.t = rest / g.L[2];
     c.b = (c.y + c.z + c.t + par) & 1;  // x = 2*xh + b
     return c;
+}
+
+// Processing order of sites.  zblk = 0: memory order (x, y, z, t).  zblk > 0: the
+// (z, t) planes of Lxh*Ly sites are visited z-block by z-block, and within a block
+// t-major then z, so that the spinor read by the +t and -t hops of neighbouring planes is
+// still in L2 when the second hop needs it (in memory order the two uses lie 2*Lz planes
+// apart).  Requires zblk | Lz; with Lxh*Ly a multiple of the block size every block stays
+// inside one plane, so loads stay coalesced.
+__device__ __forceinline__ int visit_order(int l, const Geom &g, int zblk) {
+    if (zblk <= 0) return l;
+    const int S = g.Lxh * g.L[1];
+    const int pl = l / S, within = l - pl * S;
+    const int per_zb = zblk * g.L[3];
+    const int zb = pl / per_zb, rem = pl - zb * per_zb;
+    const int t = rem / zblk, zi = rem - t * zblk;
+    return ((zb * zblk + zi) + g.L[2] * t) * S + within;
 }
 
 // Block index remapped so that each XCD (blocks are dealt round-robin to 8 XCDs)

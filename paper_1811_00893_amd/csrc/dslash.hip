@@ -14,8 +14,11 @@
 // the t projections are (0, 0, 2psi2, 2psi3) forward and (2psi0, 2psi1, 0, 0) backward,
 // so a t-hop reads only two spins of its neighbour.
 //
-// The antiperiodic time boundary is already folded into the t-links (sign on the
-// t = Lt-1 slice), so the kernel is boundary-free apart from periodic wrap-around.
+// Links are stored either in full (18 reals, antiperiodic sign folded into the t-links of
+// the t = Lt-1 slice) or, for SU(3) fields, as their first two rows (12 reals: a third
+// less link traffic, the largest part of the kernel's bytes); the third row is then
+// rebuilt as conj(row0 x row1) and the boundary sign is applied to the two t-hops that
+// cross t = Lt-1 <-> 0.
 #include <cstdio>
 
 #include "common.h"
@@ -75,21 +78,33 @@ __device__ __forceinline__ constexpr bool spin_needed(int s) {
     return MU != 3 ? true : (FWD ? s >= 2 : s < 2);
 }
 
-template <int SP, int GP, int RPT, int MU, bool FWD>
+// NE: stored complex entries per link (9, or 6 = the first two rows of an SU(3) matrix).
+// sgn: boundary sign of this hop (only used with NE == 6; full links carry it folded in).
+template <int SP, int GP, int RPT, int NE, int MU, bool FWD>
 __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
-                                        int r0, int nbr, int link_par, int link_site) {
+                                        int r0, int nbr, int link_par, int link_site, real_t<SP> sgn) {
     using R = real_t<SP>;
     const int stride = a.g.stride;
     // link U_mu(x) (forward, at the output site) or U_mu(x - mu) (backward, at the neighbour)
     Cx<R> U[3][3];
-    const size_t lbase = (size_t)((link_par * 4 + MU) * 9) * stride + link_site;
+    const unsigned loff = (unsigned)link_site * Elem<GP>::bytes;
 #pragma unroll
-    for (int e = 0; e < 9; e++) U[e / 3][e % 3] = ld_c_nt<GP, R>(a.gauge, lbase + (size_t)e * stride);
+    for (int e = 0; e < NE; e++)
+        U[e / 3][e % 3] = ld_p_nt<GP, R>(plane_ptr<GP>(a.gauge, (link_par * 4 + MU) * NE + e, stride), loff);
+    if constexpr (NE == 6) {
+        // third row of an SU(3) matrix: complex conjugate of (row 0) x (row 1)
+        const Cx<R> c0 = csub(cmul(U[0][1], U[1][2]), cmul(U[0][2], U[1][1]));
+        const Cx<R> c1 = csub(cmul(U[0][2], U[1][0]), cmul(U[0][0], U[1][2]));
+        const Cx<R> c2 = csub(cmul(U[0][0], U[1][1]), cmul(U[0][1], U[1][0]));
+        U[2][0] = {c0.re, -c0.im};
+        U[2][1] = {c1.re, -c1.im};
+        U[2][2] = {c2.re, -c2.im};
+    }
 
 #pragma unroll
     for (int r = 0; r < RPT; r++) {
         if (!act[r]) continue;
-        const size_t sbase = (size_t)(r0 + r) * 12 * stride + nbr;
+        const unsigned soff = (unsigned)nbr * Elem<SP>::bytes;
         Cx<R> p[4][3];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
@@ -102,7 +117,7 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
             const int src = a.g5in ? (s ^ 2) : s;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                Cx<R> v = ld_c<SP, R>(a.in.data, sbase + (size_t)(src * 3 + c) * stride);
+                Cx<R> v = ld_p<SP, R>(plane_ptr<SP>(a.in.data, (r0 + r) * 12 + src * 3 + c, stride), soff);
                 p[s][c] = a.g5in ? Cx<R>{-v.re, -v.im} : v;
             }
         }
@@ -126,14 +141,14 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
                     if constexpr (FWD) t = cfma(t, U[a_][b_], h[k][b_]);       // U h
                     else               t = cfma_conj(t, U[b_][a_], h[k][b_]);  // U^dag h
                 }
-                u[k][a_] = t;
+                u[k][a_] = NE == 6 && MU == 3 ? cscale(t, sgn) : t;
             }
         reconstruct<MU, FWD, R>(acc[r], u);
     }
 }
 
-template <int SP, int GP, int RPT>
-__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a, int xcd_remap) {
+template <int SP, int GP, int RPT, int NE>
+__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a, int xcd_remap, int zblk) {
     using R = real_t<SP>;
     const Geom &g = a.g;
     const int r0 = blockIdx.y * RPT;
@@ -147,9 +162,9 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a, int xcd_remap
     if (!any) return;  // uniform over the block
 
     const int tile = xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int i_raw = tile * blockDim.x + threadIdx.x;
-    const bool valid = i_raw < g.Vh;
-    const int i = valid ? i_raw : g.Vh - 1;
+    const int l = tile * blockDim.x + threadIdx.x;
+    const bool valid = l < g.Vh;
+    const int i = valid ? visit_order(l, g, zblk) : g.Vh - 1;
     const int par = a.par, opar = 1 - par;
     const SiteXY c = cb_coords(g, i, par);
     const int row = i - c.xh;
@@ -170,14 +185,17 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a, int xcd_remap
 #pragma unroll
             for (int k = 0; k < 3; k++) acc[r][s][k] = {R(0), R(0)};
 
-    hop_dir<SP, GP, RPT, 0, true>(acc, a, act, r0, xp, par, i);
-    hop_dir<SP, GP, RPT, 0, false>(acc, a, act, r0, xm, opar, xm);
-    hop_dir<SP, GP, RPT, 1, true>(acc, a, act, r0, yp, par, i);
-    hop_dir<SP, GP, RPT, 1, false>(acc, a, act, r0, ym, opar, ym);
-    hop_dir<SP, GP, RPT, 2, true>(acc, a, act, r0, zp, par, i);
-    hop_dir<SP, GP, RPT, 2, false>(acc, a, act, r0, zm, opar, zm);
-    hop_dir<SP, GP, RPT, 3, true>(acc, a, act, r0, tp, par, i);
-    hop_dir<SP, GP, RPT, 3, false>(acc, a, act, r0, tm, opar, tm);
+    const R one = R(1);
+    const R sgn_tf = (NE == 6 && c.t == g.L[3] - 1) ? -one : one;  // forward hop across t = Lt-1 -> 0
+    const R sgn_tb = (NE == 6 && c.t == 0) ? -one : one;            // backward hop across t = 0 -> Lt-1
+    hop_dir<SP, GP, RPT, NE, 0, true>(acc, a, act, r0, xp, par, i, one);
+    hop_dir<SP, GP, RPT, NE, 0, false>(acc, a, act, r0, xm, opar, xm, one);
+    hop_dir<SP, GP, RPT, NE, 1, true>(acc, a, act, r0, yp, par, i, one);
+    hop_dir<SP, GP, RPT, NE, 1, false>(acc, a, act, r0, ym, opar, ym, one);
+    hop_dir<SP, GP, RPT, NE, 2, true>(acc, a, act, r0, zp, par, i, one);
+    hop_dir<SP, GP, RPT, NE, 2, false>(acc, a, act, r0, zm, opar, zm, one);
+    hop_dir<SP, GP, RPT, NE, 3, true>(acc, a, act, r0, tp, par, i, sgn_tf);
+    hop_dir<SP, GP, RPT, NE, 3, false>(acc, a, act, r0, tm, opar, tm, sgn_tb);
 
     const int nv = red_nvals(a.red);
 #pragma unroll
@@ -246,37 +264,44 @@ bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
     if (c.rpt < 1 || c.rpt > 4) return false;
     if (a.nrhs % c.rpt != 0) return false;
     if (a.in.prec == P64 && c.rpt > 2) return false;
+    if (c.zblk < 0 || (c.zblk > 0 && a.g.L[2] % c.zblk != 0)) return false;
     return true;
 }
 
 int hop_nblocks(const HopArgs &a, const LaunchCfg &c) { return (a.g.Vh + c.block - 1) / c.block; }
 
-template <int SP, int GP>
+template <int SP, int GP, int NE>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     dim3 grid(hop_nblocks(a, c), a.nrhs / c.rpt);
     dim3 block(c.block);
     const int remap = c.xcd;
     switch (c.rpt) {
-        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1>), grid, block, 0, s, a, remap); break;
-        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2>), grid, block, 0, s, a, remap); break;
+        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE>), grid, block, 0, s, a, remap, c.zblk); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE>), grid, block, 0, s, a, remap, c.zblk); break;
         case 3:
-            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 3>), grid, block, 0, s, a, remap);
+            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 3, NE>), grid, block, 0, s, a, remap, c.zblk);
             break;
         case 4:
-            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 4>), grid, block, 0, s, a, remap);
+            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 4, NE>), grid, block, 0, s, a, remap, c.zblk);
             break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int SP, int GP>
+static hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    return a.recon == 12 ? launch_hop_t<SP, GP, 6>(a, c, s) : launch_hop_t<SP, GP, 9>(a, c, s);
+}
+
 hipError_t launch_hop(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     if (!hop_cfg_valid(a, c)) return hipErrorInvalidValue;
     const int sp = a.in.prec, gp = a.gprec;
-    if (sp == P64 && gp == P64) return launch_hop_t<P64, P64>(a, c, s);
-    if (sp == P32 && gp == P32) return launch_hop_t<P32, P32>(a, c, s);
-    if (sp == P16 && gp == P16) return launch_hop_t<P16, P16>(a, c, s);
-    if (sp == P16 && gp == P32) return launch_hop_t<P16, P32>(a, c, s);
+    if (a.recon != 12 && a.recon != 18) return hipErrorInvalidValue;
+    if (sp == P64 && gp == P64) return launch_hop_r<P64, P64>(a, c, s);
+    if (sp == P32 && gp == P32) return launch_hop_r<P32, P32>(a, c, s);
+    if (sp == P16 && gp == P16) return launch_hop_r<P16, P16>(a, c, s);
+    if (sp == P16 && gp == P32) return launch_hop_r<P16, P32>(a, c, s);
     return hipErrorInvalidValue;
 }
 

@@ -3,9 +3,13 @@
 //   * canonical complex128 spinors [rhs][site][spin][colour]  <->  parity-split planes;
 //   * FP64 -> FP32 / FP16-with-per-site-scale encodings (FP16: scale s = max |component|
 //     over the 24 reals of the site in FP32, h = fp16_rne(fp32(v / s)));
-//   * gauge packing: canonical links -> parity-split planes with the antiperiodic sign of
-//     the time boundary folded into U_t(x) on the slice t = Lt - 1 (that link carries
-//     both the forward hop out of t = Lt-1 and the backward hop out of t = 0);
+//   * gauge packing: canonical links -> parity-split planes.  Full (18-real) links carry
+//     the antiperiodic sign of the time boundary folded into U_t(x) on the slice
+//     t = Lt - 1 (that link serves both the forward hop out of t = Lt-1 and the backward
+//     hop out of t = 0).  SU(3) links may instead be stored as their first two rows
+//     (12 reals): the third row of a special unitary matrix is the complex conjugate of
+//     the cross product of the first two, and the hop kernel rebuilds it and applies the
+//     boundary sign itself (a folded sign would flip det U and break that identity);
 //   * the defect-correction glue (scaled conversion of the residual, FP64 accumulation
 //     of the correction), and a plain streaming copy used as a bandwidth reference.
 #include "common.h"
@@ -95,26 +99,84 @@ __global__ void __launch_bounds__(256) axpy_f64_kernel(Spinor x, Spinor e, Geom 
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) gauge_pack_kernel(void *dst, const double2 *canon, Geom g) {
+__global__ void __launch_bounds__(256) gauge_pack_kernel(void *dst, const double2 *canon, Geom g, int recon) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.Vh) return;
     const int par = blockIdx.y >> 2, mu = blockIdx.y & 3;
     int t;
     const int s = full_site(g, i, par, &t);
-    const double sgn = (mu == 3 && t == g.L[3] - 1) ? -1.0 : 1.0;
+    const int ne = recon == 12 ? 6 : 9;
+    const double sgn = (recon == 18 && mu == 3 && t == g.L[3] - 1) ? -1.0 : 1.0;
     const double2 *src = canon + ((size_t)s * 4 + mu) * 9;
     using R = real_t<P>;
-    const size_t base = (size_t)((par * 4 + mu) * 9) * g.stride + i;
-#pragma unroll
-    for (int e = 0; e < 9; e++) {
+    const size_t base = (size_t)((par * 4 + mu) * ne) * g.stride + i;
+    for (int e = 0; e < ne; e++) {
         const double2 d = src[e];
         st_c<P, R>(dst, base + (size_t)e * g.stride, Cx<R>{(R)(sgn * d.x), (R)(sgn * d.y)});
     }
 }
 
-__global__ void stream_copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16) {
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
-        dst[k] = src[k];
+// max over entries of |U U^dag - 1| and |det U - 1| for each link; flag if above tol
+__global__ void su3_check_kernel(const double2 *canon, size_t nlinks, double tol, int *flag) {
+    bool bad = false;
+    for (size_t l = blockIdx.x * (size_t)blockDim.x + threadIdx.x; l < nlinks; l += (size_t)gridDim.x * blockDim.x) {
+        Cx<double> u[3][3];
+        for (int e = 0; e < 9; e++) u[e / 3][e % 3] = {canon[l * 9 + e].x, canon[l * 9 + e].y};
+        double dev = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                Cx<double> acc = {a == b ? -1.0 : 0.0, 0.0};
+                for (int k = 0; k < 3; k++) acc = cfma_conj(acc, u[b][k], u[a][k]);  // (U U^dag)_ab - d_ab
+                dev = fmax(dev, fabs(acc.re) + fabs(acc.im));
+            }
+        // det via the first row and the cofactors of rows 1, 2
+        const Cx<double> c0 = csub(cmul(u[1][1], u[2][2]), cmul(u[1][2], u[2][1]));
+        const Cx<double> c1 = csub(cmul(u[1][2], u[2][0]), cmul(u[1][0], u[2][2]));
+        const Cx<double> c2 = csub(cmul(u[1][0], u[2][1]), cmul(u[1][1], u[2][0]));
+        const Cx<double> det = cadd(cadd(cmul(u[0][0], c0), cmul(u[0][1], c1)), cmul(u[0][2], c2));
+        dev = fmax(dev, fabs(det.re - 1.0) + fabs(det.im));
+        bad |= !(dev <= tol);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// Streaming copy: each thread moves 4 x 16 bytes per step (4 loads in flight before the
+// stores), grid-strided over the buffer.
+__global__ void __launch_bounds__(256) stream_copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                          size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (; k + 3 * stride < n16; k += 4 * stride) {
+        const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
+        dst[k] = a;
+        dst[k + stride] = b;
+        dst[k + 2 * stride] = c;
+        dst[k + 3 * stride] = d;
+    }
+    for (; k < n16; k += stride) dst[k] = src[k];
+}
+
+// Read-only stream: sums the buffer as 32-bit words (4 x 16-byte loads in flight per
+// thread) and writes one word per block so the loads cannot be elided.
+__global__ void __launch_bounds__(256) stream_read_kernel(const uint4 *__restrict__ src, size_t n16,
+                                                          unsigned *sink) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    unsigned acc = 0;
+    for (; k + 3 * stride < n16; k += 4 * stride) {
+        const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
+        acc += a.x ^ b.y ^ c.z ^ d.w;
+        acc += a.w ^ b.x ^ c.y ^ d.z;
+    }
+    for (; k < n16; k += stride) acc += src[k].x;
+    __shared__ unsigned red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = 0;
+        for (int j = 0; j < (int)blockDim.x; j++) t += red[j];
+        sink[blockIdx.x] = t;
+    }
 }
 
 __global__ void copy_tail_kernel(unsigned char *dst, const unsigned char *src, size_t n) {
@@ -131,6 +193,7 @@ __global__ void check_finite_kernel(const double *p, size_t n, int *flag) {
 
 // ---------------------------------------------------------------------------------
 static inline dim3 site_grid(const Geom &g, int ny) { return dim3((g.Vh + 255) / 256, ny); }
+constexpr unsigned kStreamBlocks = 8192;  // 32 blocks of 256 threads per CU
 
 hipError_t launch_to_parity(Spinor f, const double *canon, const Geom &g, int par, int nrhs, double scale,
                             hipStream_t s) {
@@ -182,15 +245,28 @@ hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const 
     return hipGetLastError();
 }
 
-hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geom &g, hipStream_t s) {
+hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geom &g, int recon, hipStream_t s) {
+    if (recon != 12 && recon != 18) return hipErrorInvalidValue;
     const dim3 grid = site_grid(g, 8), block(256);
     const double2 *c = reinterpret_cast<const double2 *>(canon);
     switch (prec) {
-        case P64: hipLaunchKernelGGL(gauge_pack_kernel<P64>, grid, block, 0, s, dst, c, g); break;
-        case P32: hipLaunchKernelGGL(gauge_pack_kernel<P32>, grid, block, 0, s, dst, c, g); break;
-        case P16: hipLaunchKernelGGL(gauge_pack_kernel<P16>, grid, block, 0, s, dst, c, g); break;
+        case P64: hipLaunchKernelGGL(gauge_pack_kernel<P64>, grid, block, 0, s, dst, c, g, recon); break;
+        case P32: hipLaunchKernelGGL(gauge_pack_kernel<P32>, grid, block, 0, s, dst, c, g, recon); break;
+        case P16: hipLaunchKernelGGL(gauge_pack_kernel<P16>, grid, block, 0, s, dst, c, g, recon); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_su3_check(const double *canon, size_t nlinks, double tol, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(su3_check_kernel, dim3(2048), dim3(256), 0, s, reinterpret_cast<const double2 *>(canon),
+                       nlinks, tol, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const void *src, size_t bytes, unsigned *sink, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    hipLaunchKernelGGL(stream_read_kernel, dim3(kStreamBlocks), dim3(256), 0, s, (const uint4 *)src, n16, sink);
     return hipGetLastError();
 }
 
@@ -198,7 +274,7 @@ hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStrea
     const size_t n16 = bytes / 16;
     if (n16) {
         const size_t want = (n16 + 255) / 256;
-        const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+        const unsigned blocks = (unsigned)(want < kStreamBlocks ? want : kStreamBlocks);
         hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n16);
     }
     const size_t tail = bytes - n16 * 16;

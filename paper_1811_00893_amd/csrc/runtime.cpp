@@ -85,7 +85,7 @@ size_t partials_doubles(const Geom &g, int nrhs) {
 
 double hop_bytes(const HopArgs &a) {
     const double sb = 24.0 * real_bytes(a.in.prec) + (a.in.prec == P16 ? 4.0 : 0.0);
-    const double lb = 8.0 * 18.0 * real_bytes(a.gprec);
+    const double lb = 8.0 * 18.0 * real_bytes(a.gprec);  // algorithmic: a link is 18 reals
     double per_rhs = sb;                 // input field, each site once
     if (!a.nostore) per_rhs += sb;       // output
     if (a.has_y) per_rhs += sb;
@@ -135,6 +135,9 @@ void wilson_ctx::load_tune_cache() {
     tune_loaded = true;
     const char *env = std::getenv("WILSON_TUNE");
     if (env && std::strcmp(env, "0") == 0) tune_enabled = false;
+    const char *fc = std::getenv("WILSON_HOP_CFG");
+    if (fc && std::sscanf(fc, "%d,%d,%d,%d", &forced_cfg.block, &forced_cfg.rpt, &forced_cfg.xcd, &forced_cfg.zblk) == 4)
+        forced = true;
     const char *path = std::getenv("WILSON_TUNE_CACHE");
     if (!path || !*path) return;
     tune_path = path;
@@ -148,7 +151,8 @@ void wilson_ctx::load_tune_cache() {
         if (k1 == std::string::npos) continue;
         const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
         LaunchCfg c;
-        if (std::sscanf(line.c_str() + k1, "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d", &c.block, &c.rpt, &c.xcd) == 3)
+        if (std::sscanf(line.c_str() + k1, "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d", &c.block,
+                        &c.rpt, &c.xcd, &c.zblk) == 4)
             tuned[key] = c;
     }
 }
@@ -157,14 +161,14 @@ void wilson_ctx::save_tune_entry(const std::string &key, const LaunchCfg &c, dou
     if (tune_path.empty()) return;
     std::ofstream out(tune_path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
-        << ", \"ms\": " << ms << "}\n";
+        << ", \"zblk\": " << c.zblk << ", \"ms\": " << ms << "}\n";
 }
 
 namespace wl {
 
 static std::string hop_key(const HopArgs &a) {
     std::ostringstream os;
-    os << "hop sp=" << a.in.prec << " gp=" << a.gprec << " nrhs=" << a.nrhs << " red=" << a.red << " y=" << a.has_y
+    os << "hop sp=" << a.in.prec << " gp=" << a.gprec << " rc=" << a.recon << " nrhs=" << a.nrhs << " red=" << a.red << " y=" << a.has_y
        << " dims=" << a.g.L[0] << "x" << a.g.L[1] << "x" << a.g.L[2] << "x" << a.g.L[3];
     return os.str();
 }
@@ -185,13 +189,16 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
     std::vector<LaunchCfg> cands;
     for (int block : {64, 128, 256})
         for (int rpt : {1, 2, 3, 4})
-            for (int xcd : {0, 1}) {
-                LaunchCfg c;
-                c.block = block;
-                c.rpt = rpt;
-                c.xcd = xcd;
-                if (hop_cfg_valid(a, c)) cands.push_back(c);
-            }
+            for (int xcd : {0, 1})
+                for (int zblk : {0, 2, 4, 8}) {
+                    if (xcd == 0 && zblk != 0) continue;  // plane blocking only matters per XCD
+                    LaunchCfg c;
+                    c.block = block;
+                    c.rpt = rpt;
+                    c.xcd = xcd;
+                    c.zblk = zblk;
+                    if (hop_cfg_valid(a, c)) cands.push_back(c);
+                }
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
@@ -207,6 +214,9 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         float ms = 0.f;
         WL_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
+        if (std::getenv("WILSON_TUNE_VERBOSE"))
+            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d: %.2f us\n", hop_key(a).c_str(), c.block,
+                         c.rpt, c.xcd, c.zblk, per * 1e3);
         if (per < bms) {
             bms = per;
             best = c;
@@ -226,7 +236,13 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
     const std::string key = hop_key(a);
     LaunchCfg cfg;
     auto it = ctx->tuned.find(key);
-    if (it != ctx->tuned.end() && hop_cfg_valid(a, it->second)) {
+    if (ctx->forced) {
+        cfg = ctx->forced_cfg;
+        if (!hop_cfg_valid(a, cfg)) {  // keep the pinned order and block, fit the RHS split
+            cfg.rpt = default_cfg(a).rpt;
+            if (cfg.zblk > 0 && a.g.L[2] % cfg.zblk) cfg.zblk = 0;
+        }
+    } else if (it != ctx->tuned.end() && hop_cfg_valid(a, it->second)) {
         cfg = it->second;
     } else if (ctx->tune_enabled && a.g.Vh >= 4096) {
         double ms = 0;

@@ -84,6 +84,7 @@ struct wilson_gauge {
     wl::Geom g;
     int32_t dims[4];
     wl::DevBuf U[3];  // per wl::Prec
+    int recon = 18;   // 12: links stored as two rows (SU(3) verified at upload)
     size_t bytes() const { return U[0].size() + U[1].size() + U[2].size(); }
     const void *links(int prec) const { return U[prec].get(); }
 };
@@ -112,6 +113,8 @@ struct wilson_ctx {
     // ---- autotuner ----
     std::map<std::string, wl::LaunchCfg> tuned;
     bool tune_enabled = true;
+    bool forced = false;   // WILSON_HOP_CFG="block,rpt,xcd,zblk" pins every hop launch (tests)
+    wl::LaunchCfg forced_cfg;
     bool tune_loaded = false;
     std::string tune_path;
     void load_tune_cache();

@@ -127,6 +127,7 @@ class EoCore {
         a.in = V(in);
         a.gauge = links(in.prec);
         a.gprec = lprec(in.prec);
+        a.recon = G->recon;
         a.partials = part();
         return a;
     }
@@ -603,6 +604,7 @@ void dslash_device(wilson_ctx *ctx, const wilson_gauge *G, double *out, const do
         a.in = par ? ws->in_e.f : ws->in_o.f;
         a.gauge = G->links(P == P64 ? P64 : GP);
         a.gprec = P == P64 ? P64 : GP;
+        a.recon = G->recon;
         for (int k = 0; k < nrhs; k++) a.cH[k] = -kappa;
         if (parity == 2) {
             a.has_y = 1;

@@ -273,3 +273,27 @@ def test_full_size_sampled_dslash(L, ctx):
     L.wilson_gauge_free(ctx, g)
     del U, psi, out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2"])
+def test_dslash_every_launch_config(L, cfg, monkeypatch):
+    """Every hop launch configuration the tuner can pick (block size, RHS per thread,
+    XCD tile order, plane-blocked visiting order) gives the oracle's result; the lattice
+    has a ragged last block for every block size."""
+    monkeypatch.setenv("WILSON_HOP_CFG", cfg)
+    dims = (6, 4, 8, 10)  # Vh = 960: not a multiple of 64, 128 or 256
+    U, _ = setup_case(dims, 9)
+    nrhs = 4
+    psi = inputs.gaussian_source(dims, seed=31, nrhs=nrhs)
+    c = L.wilson_context_create()
+    g = L.wilson_gauge_load(c, U.to(DEV), dims, L.WILSON_GAUGE_FP32)
+    try:
+        for prec, lim in ((0, 1e-12), (1, 5e-7)):
+            out = torch.zeros_like(psi, device=DEV)
+            L.check(L.wilson_dslash_ex(c, g, out, psi.to(DEV), 0.125, 2, prec, nrhs), "dslash")
+            for k in range(nrhs):
+                ref = oracle.apply_D(psi[k].numpy(), U.numpy(), 0.125, dims)
+                assert rel(out[k].cpu().numpy(), ref) < lim
+    finally:
+        L.wilson_gauge_free(c, g)
+        L.wilson_context_destroy(c)
