@@ -1,0 +1,241 @@
+"""Continuous-batching solve server over the library's batch step API.
+
+Requests (a resident gauge field, kappa, tolerance, 1..12 right-hand sides) arrive over
+time.  Each resident gauge field gets one batch of `nslots` solve slots in the library
+(`wilson_batch_*`), on its own HIP stream.  The loop repeatedly
+  * admits waiting requests: each right-hand side takes a free slot of its gauge field's
+    batch as soon as one frees up (a request may be partly running while the rest of its
+    right-hand sides wait); a new batch is created only if its device footprint fits in
+    the HBM budget next to everything already resident;
+  * enqueues `step_iters` iterations on every batch with running slots (all streams are
+    fed before any is waited on, so batches of different lattices overlap on the GPU);
+  * polls every batch, copies finished solutions out and frees their slots;
+  * completes a request when all its right-hand sides are done, recording latency
+    from arrival to solution-on-host.
+Each slot is an independent solve (own scalars, own kappa and tolerance, reductions
+per slot in a fixed order), so a request's result does not depend on what else runs.
+
+The scheduler (`Scheduler`) is plain host logic over an engine interface; `LibEngine`
+is the real engine.  Tests drive the scheduler with a simulated engine and clock.
+"""
+import collections
+import dataclasses
+import time
+from typing import Any, Dict, List, Optional
+
+FREE, RUNNING, FINISHED = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    gauge_id: Any
+    kappa: float
+    tol: float
+    b: Any                      # (nrhs, V, 4, 3) complex128 (host or device)
+    arrival: float = 0.0
+    maxiter: int = 20000
+    # filled by the scheduler
+    x: Any = None
+    pending: List[int] = dataclasses.field(default_factory=list)  # RHS indices not yet attached
+    running: int = 0
+    done_rhs: int = 0
+    status: List[int] = dataclasses.field(default_factory=list)
+    info: List[dict] = dataclasses.field(default_factory=list)
+    finish: Optional[float] = None
+    rejected: bool = False
+
+    @property
+    def nrhs(self):
+        return int(self.b.shape[0])
+
+    @property
+    def latency(self):
+        return None if self.finish is None else self.finish - self.arrival
+
+
+class Scheduler:
+    """Admission, slot assignment, stepping and retirement (engine-agnostic)."""
+
+    def __init__(self, engine, hbm_budget: float, nslots: int = 12, step_iters: int = 8, clock=time.perf_counter):
+        self.engine = engine
+        self.budget = float(hbm_budget)
+        self.nslots = nslots
+        self.step_iters = step_iters
+        self.clock = clock
+        self.gauges: Dict[Any, dict] = {}      # gauge_id -> {"dims", "bytes"}
+        self.batches: Dict[Any, dict] = {}     # gauge_id -> {"handle", "slots": [(req, k) | None], "bytes"}
+        self.waiting: collections.deque = collections.deque()
+        self.completed: List[Request] = []
+        self.rejected: List[Request] = []
+
+    # ---- resources ----
+    def resident_bytes(self):
+        return sum(g["bytes"] for g in self.gauges.values()) + sum(b["bytes"] for b in self.batches.values())
+
+    def register_gauge(self, gauge_id, dims, nbytes):
+        self.gauges[gauge_id] = {"dims": tuple(dims), "bytes": float(nbytes)}
+
+    def submit(self, req: Request):
+        req.arrival = self.clock() if not req.arrival else req.arrival
+        req.pending = list(range(req.nrhs))
+        req.status = [None] * req.nrhs
+        req.info = [None] * req.nrhs
+        req.x = self.engine.alloc_solution(req)
+        g = self.gauges.get(req.gauge_id)
+        need = self.engine.batch_bytes(g["dims"], self.nslots) if g else float("inf")
+        if g is None or g["bytes"] + need > self.budget:
+            req.rejected = True   # can never fit
+            self.rejected.append(req)
+            return False
+        self.waiting.append(req)
+        return True
+
+    def _batch_for(self, gauge_id):
+        b = self.batches.get(gauge_id)
+        if b is not None:
+            return b
+        dims = self.gauges[gauge_id]["dims"]
+        need = self.engine.batch_bytes(dims, self.nslots)
+        if self.resident_bytes() + need > self.budget:
+            self._evict_idle(need)
+            if self.resident_bytes() + need > self.budget:
+                return None
+        handle = self.engine.create_batch(gauge_id, self.nslots)
+        b = {"handle": handle, "slots": [None] * self.nslots, "bytes": need}
+        self.batches[gauge_id] = b
+        return b
+
+    def _evict_idle(self, need):
+        for gid in list(self.batches):
+            b = self.batches[gid]
+            if all(s is None for s in b["slots"]) and not any(r.gauge_id == gid for r in self.waiting):
+                self.engine.destroy_batch(b["handle"])
+                del self.batches[gid]
+                if self.resident_bytes() + need <= self.budget:
+                    return
+
+    # ---- one turn of the loop ----
+    def admit(self):
+        still = collections.deque()
+        while self.waiting:
+            req = self.waiting.popleft()
+            b = self._batch_for(req.gauge_id)
+            if b is not None:
+                for k, slot in enumerate(b["slots"]):
+                    if not req.pending:
+                        break
+                    if slot is None:
+                        j = req.pending.pop(0)
+                        self.engine.attach(b["handle"], k, req, j)
+                        b["slots"][k] = (req, j)
+                        req.running += 1
+            if req.pending:
+                still.append(req)
+        self.waiting = still
+
+    def step(self):
+        active = [b for b in self.batches.values() if any(s is not None for s in b["slots"])]
+        for b in active:                       # enqueue on every stream first ...
+            self.engine.step(b["handle"], self.step_iters)
+        for b in active:                       # ... then wait on each
+            state, status = self.engine.poll(b["handle"])
+            for k, slot in enumerate(b["slots"]):
+                if slot is None or state[k] != FINISHED:
+                    continue
+                req, j = slot
+                st, info = self.engine.detach(b["handle"], k, req, j)
+                req.status[j] = st
+                req.info[j] = info
+                req.running -= 1
+                req.done_rhs += 1
+                b["slots"][k] = None
+                if req.done_rhs == req.nrhs:
+                    self.engine.finish(req)
+                    req.finish = self.clock()
+                    self.completed.append(req)
+
+    def busy(self):
+        return bool(self.waiting) or any(any(s is not None for s in b["slots"]) for b in self.batches.values())
+
+    def run_until_idle(self, max_turns=10 ** 7):
+        for _ in range(max_turns):
+            if not self.busy():
+                return
+            self.admit()
+            self.step()
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        for b in self.batches.values():
+            self.engine.destroy_batch(b["handle"])
+        self.batches.clear()
+
+
+class LibEngine:
+    """Engine on libwilson.so: one context and HIP stream per resident gauge field."""
+
+    def __init__(self, precision=1, solver=0, inner_tol=0.0, device="cuda:0"):
+        import torch
+
+        from . import _lib
+        self.L = _lib
+        self.torch = torch
+        self.device = torch.device(device)
+        self.opts = {"precision": precision, "solver": solver, "inner_tol": inner_tol, "maxiter": 100000}
+        self.gauge = {}    # gauge_id -> (ctx, handle, dims, stream)
+        self.outputs = {}
+
+    def load_gauge(self, gauge_id, U, dims):
+        torch = self.torch
+        stream = torch.cuda.Stream(device=self.device)  # default priority
+        ctx = self.L.wilson_context_create(stream)
+        bits = self.L.WILSON_GAUGE_FP32 | (self.L.WILSON_GAUGE_FP16 if self.opts["precision"] == 2 else 0)
+        g = self.L.wilson_gauge_load(ctx, U, dims, bits)
+        self.gauge[gauge_id] = (ctx, g, tuple(dims), stream)
+        return self.L.wilson_gauge_bytes(g)
+
+    def batch_bytes(self, dims, nslots):
+        return self.L.wilson_footprint_bytes(dims, nslots, self.opts)
+
+    def create_batch(self, gauge_id, nslots):
+        ctx, g, dims, stream = self.gauge[gauge_id]
+        return (gauge_id, self.L.wilson_batch_create(ctx, g, nslots, self.opts), nslots)
+
+    def destroy_batch(self, handle):
+        self.L.wilson_batch_destroy(handle[1])
+
+    def alloc_solution(self, req):
+        return self.torch.zeros(tuple(req.b.shape), dtype=self.torch.complex128)
+
+    def attach(self, handle, slot, req, j):
+        b = req.b[j]
+        if not b.is_contiguous():
+            b = b.contiguous()
+        st = self.L.wilson_batch_attach(handle[1], slot, b, req.kappa, req.tol, req.maxiter)
+        self.L.check(st, "wilson_batch_attach")
+
+    def step(self, handle, iters):
+        self.L.wilson_batch_step(handle[1], iters)
+
+    def poll(self, handle):
+        return self.L.wilson_batch_poll(handle[1], handle[2])
+
+    def detach(self, handle, slot, req, j):
+        out = req.x[j]
+        st, info = self.L.wilson_batch_detach(handle[1], slot, out)
+        return st, info
+
+    def finish(self, req):
+        pass
+
+    def close(self):
+        for gid, (ctx, g, dims, stream) in self.gauge.items():
+            self.L.wilson_gauge_free(ctx, g)
+            self.L.wilson_context_destroy(ctx)
+        self.gauge.clear()
+
+
+def make_server(hbm_budget, nslots=12, step_iters=8, precision=1, solver=0):
+    eng = LibEngine(precision=precision, solver=solver)
+    return Scheduler(eng, hbm_budget, nslots=nslots, step_iters=step_iters), eng

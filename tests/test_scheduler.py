@@ -1,0 +1,146 @@
+"""Serving policy of the continuous-batching scheduler, driven by a simulated engine and
+clock (a test double of the engine interface only; the real engine is the library's batch
+API, exercised in the GPU tests)."""
+import numpy as np
+import pytest
+
+from paper_1811_00893_amd.serve import FINISHED, FREE, RUNNING, Request, Scheduler
+
+
+class FakeEngine:
+    """Each attached RHS finishes after `need` iterations (kappa-dependent); one step of
+    `iters` iterations advances every running slot."""
+
+    def __init__(self, batch_bytes=100.0):
+        self.bb = batch_bytes
+        self.batches = {}
+        self.created = 0
+        self.destroyed = 0
+        self.steps = 0
+
+    def batch_bytes(self, dims, nslots):
+        return self.bb
+
+    def create_batch(self, gid, nslots):
+        self.created += 1
+        h = (gid, self.created)
+        self.batches[h] = [None] * nslots
+        return h
+
+    def destroy_batch(self, h):
+        self.destroyed += 1
+        del self.batches[h]
+
+    def alloc_solution(self, req):
+        return np.zeros(req.b.shape)
+
+    def attach(self, h, k, req, j):
+        assert self.batches[h][k] is None, "slot double-booked"
+        need = int(round(1000 * req.kappa)) + j
+        self.batches[h][k] = [need, 0, req.rid, j]
+
+    def step(self, h, iters):
+        self.steps += 1
+        for s in self.batches[h]:
+            if s is not None:
+                s[1] += iters
+
+    def poll(self, h):
+        st = np.array([FREE if s is None else (FINISHED if s[1] >= s[0] else RUNNING) for s in self.batches[h]])
+        return st, np.zeros_like(st)
+
+    def detach(self, h, k, req, j):
+        s = self.batches[h][k]
+        assert s[2] == req.rid and s[3] == j
+        req.x[j] = req.rid * 100 + j
+        self.batches[h][k] = None
+        return 0, {"iterations": s[1]}
+
+    def finish(self, req):
+        pass
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1.0
+        return self.t
+
+
+def mkreq(rid, gid, nrhs, kappa=0.01):
+    return Request(rid=rid, gauge_id=gid, kappa=kappa, tol=1e-10, b=np.zeros((nrhs, 4)))
+
+
+def test_slots_refill_and_requests_complete():
+    eng = FakeEngine()
+    sch = Scheduler(eng, hbm_budget=1000, nslots=4, step_iters=5, clock=Clock())
+    sch.register_gauge("g", (4, 4, 4, 4), 50)
+    reqs = [mkreq(i, "g", nrhs=n) for i, n in enumerate([3, 3, 2, 5])]
+    for r in reqs:
+        assert sch.submit(r)
+    sch.admit()
+    b = sch.batches["g"]
+    # 4 slots: request 0 takes 3, request 1 takes the last one, the rest wait
+    assert [s[0].rid for s in b["slots"]] == [0, 0, 0, 1]
+    assert reqs[1].pending == [1, 2] and len(sch.waiting) == 3
+    sch.run_until_idle()
+    assert sorted(r.rid for r in sch.completed) == [0, 1, 2, 3]
+    for r in reqs:
+        assert list(r.x[:, 0]) == [r.rid * 100 + j for j in range(r.nrhs)]
+        assert all(s == 0 for s in r.status)
+        assert r.latency is not None and r.latency > 0
+    assert eng.created == 1
+
+
+def test_admission_by_memory_budget_and_rejection():
+    """Resident gauge fields and batch workspaces must fit the HBM budget together; a
+    request whose field plus one batch can never fit is rejected at once."""
+    eng = FakeEngine(batch_bytes=100)
+    sch = Scheduler(eng, hbm_budget=300, nslots=2, step_iters=10, clock=Clock())
+    sch.register_gauge("a", (4, 4, 4, 4), 30)
+    sch.register_gauge("b", (4, 4, 4, 4), 30)
+    assert not sch.submit(mkreq(9, "unknown", 1))
+    assert sch.submit(mkreq(0, "a", 2))
+    assert sch.submit(mkreq(1, "b", 2))
+    sch.admit()
+    # 30 + 30 (fields) + 100 + 100 (two batches) = 260 <= 300
+    assert set(sch.batches) == {"a", "b"}
+    assert sch.resident_bytes() <= 300
+    sch.run_until_idle()
+    assert len(sch.completed) == 2
+    small = Scheduler(FakeEngine(batch_bytes=100), hbm_budget=120, nslots=2, clock=Clock())
+    small.register_gauge("c", (4, 4, 4, 4), 30)
+    assert not small.submit(mkreq(3, "c", 1))  # 30 + 100 > 120: can never run
+    assert small.rejected and small.rejected[0].rid == 3
+
+
+def test_idle_batches_are_evicted_to_admit_new_ones():
+    eng = FakeEngine(batch_bytes=100)
+    sch = Scheduler(eng, hbm_budget=200, nslots=2, step_iters=50, clock=Clock())
+    for g in ("a", "b"):
+        sch.register_gauge(g, (4, 4, 4, 4), 10)
+    sch.submit(mkreq(0, "a", 1))
+    sch.run_until_idle()
+    assert "a" in sch.batches
+    sch.submit(mkreq(1, "b", 1))  # 10 + 10 + 100 + 100 > 200: idle batch a must go
+    sch.run_until_idle()
+    assert "a" not in sch.batches and eng.destroyed == 1
+    assert len(sch.completed) == 2
+
+
+def test_result_independent_of_mix():
+    """A request's slots see only their own RHS: same outputs alone and mixed."""
+    def run(mix):
+        eng = FakeEngine()
+        sch = Scheduler(eng, hbm_budget=1e9, nslots=3, step_iters=7, clock=Clock())
+        sch.register_gauge("g", (4, 4, 4, 4), 1)
+        target = mkreq(42, "g", 4, kappa=0.013)
+        for r in ([mkreq(i, "g", 2, kappa=0.02 + 0.001 * i) for i in range(mix)] + [target]):
+            sch.submit(r)
+        sch.run_until_idle()
+        return target.x.copy(), [i["iterations"] >= 13 for i in target.info]
+    a = run(0)
+    b = run(5)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
