@@ -10,7 +10,7 @@ the dominant kernel (the parity hop, measured with HIP events on the library's s
 over the timed region) against the MI355X HBM peak, a Dslash-only figure (parity hop
 alone), and the CPU oracle timed on a bounded sample of the same workload.
 
-Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | batched24.
+Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | batched24 | serve.
 """
 import argparse
 import json
@@ -34,6 +34,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--dslash-only", action="store_true", help="only the Dslash section and the copy probe")
+    p.add_argument("--requests", type=int, default=40, help="serving: number of requests")
+    p.add_argument("--load", type=float, default=0.8, help="serving: offered load / FIFO capacity")
+    p.add_argument("--step-iters", type=int, default=8, help="serving: iterations per scheduler turn")
+    p.add_argument("--hbm-budget", type=float, default=200e9, help="serving: device bytes for fields + batches")
     return p.parse_args()
 
 
@@ -56,12 +60,126 @@ WORKLOADS = {
 }
 
 
+def run_serving(args):
+    """Serving: a Poisson stream of solve requests over four lattice sizes, each request on
+    one of two seeded gauge fields per size (eps ~ U[0.2, 0.4]), kappa ~ U[0.115, 0.125],
+    tol in {1e-8, 1e-10, 1e-12}, 1-12 Gaussian right-hand sides; mixed precision (FP32 inner,
+    FP64 outer).  The same trace is first served one request at a time (FIFO, the plain
+    path) to measure its capacity; arrivals are then generated at `--load` x that capacity
+    and replayed through the continuous-batching server.  Latency = arrival -> solution in
+    device memory.  FIFO latencies on the same arrivals follow from its measured service
+    times (one request at a time)."""
+    import numpy as np
+    import torch
+
+    from paper_1811_00893_amd import _lib as L
+    from paper_1811_00893_amd import inputs
+    from paper_1811_00893_amd.serve import Request, make_server
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(3000)
+    sizes = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+    pool = {}
+    for si, d in enumerate(sizes):
+        for k in range(2):
+            pool[(si, k)] = (d, float(rng.uniform(0.2, 0.4)), 3100 + 10 * si + k)
+    nreq = args.requests
+    trace = []
+    for i in range(nreq):
+        si = int(rng.integers(0, 4))
+        k = int(rng.integers(0, 2))
+        trace.append(dict(gid=(si, k), kappa=float(rng.uniform(0.115, 0.125)),
+                          tol=float([1e-8, 1e-10, 1e-12][int(rng.integers(0, 3))]),
+                          nrhs=int(rng.integers(1, 13)), seed=4000 + i))
+    U = {gid: inputs.gauge_field(d, eps=e, seed=s, device=dev) for gid, (d, e, s) in pool.items()}
+    B = [inputs.gaussian_source(pool[t["gid"]][0], seed=t["seed"], nrhs=t["nrhs"], device=dev) for t in trace]
+    opts = {"precision": 1, "maxiter": 100000}
+
+    # FIFO: one request at a time through wilson_solve_ex (all its RHS together)
+    ctx = L.wilson_context_create()
+    G = {gid: L.wilson_gauge_load(ctx, U[gid], pool[gid][0], L.WILSON_GAUGE_FP32) for gid in pool}
+    def fifo_once(i):
+        t = trace[i]
+        x = torch.zeros_like(B[i])
+        st, info = L.wilson_solve_ex(ctx, G[t["gid"]], x, B[i], t["nrhs"], t["kappa"], t["tol"], opts)
+        L.check(st, "fifo solve")
+    for i in range(min(4, nreq)):  # warm the tuner
+        fifo_once(i)
+    service = []
+    torch.cuda.synchronize()
+    for i in range(nreq):
+        s0 = time.perf_counter()
+        fifo_once(i)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - s0)
+    for g in G.values():
+        L.wilson_gauge_free(ctx, g)
+    L.wilson_context_destroy(ctx)
+    fifo_total = sum(service)
+    cap = nreq / fifo_total
+    lam = args.load * cap
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
+    # FIFO latencies on these arrivals
+    t_free, fifo_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        start = max(a, t_free)
+        t_free = start + sv
+        fifo_lat.append(t_free - a)
+
+    # continuous batching
+    sch, eng = make_server(hbm_budget=args.hbm_budget, nslots=12, step_iters=args.step_iters, precision=1)
+    for gid, (d, e, s) in pool.items():
+        sch.register_gauge(gid, d, eng.load_gauge(gid, U[gid], d))
+    warm = Request(rid=-1, gauge_id=(0, 0), kappa=0.12, tol=1e-10, b=B[0][:1].contiguous())
+    sch.submit(warm)
+    sch.run_until_idle()
+    sch.completed.clear()
+    reqs = [Request(rid=i, gauge_id=t["gid"], kappa=t["kappa"], tol=t["tol"], b=B[i], maxiter=100000)
+            for i, t in enumerate(trace)]
+    eng.alloc_solution = lambda req: torch.zeros_like(req.b)
+    t0 = time.perf_counter()
+    sch.clock = lambda: time.perf_counter() - t0
+    nxt = 0
+    while nxt < nreq or sch.busy():
+        now = sch.clock()
+        while nxt < nreq and arrivals[nxt] <= now:
+            reqs[nxt].arrival = float(arrivals[nxt])
+            sch.submit(reqs[nxt])
+            nxt += 1
+        if sch.busy():
+            sch.admit()
+            sch.step()
+        elif nxt < nreq:
+            time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
+    wall = sch.clock()
+    sch.close()
+    eng.close()
+    lat = [r.latency for r in sch.completed]
+    bad = [r.rid for r in sch.completed if any(st != 0 for st in r.status)]
+    rhs = sum(t["nrhs"] for t in trace)
+    return {
+        "metric": METRIC, "workload": "serving", "unit": "solves/s",
+        "value": rhs / wall,
+        "requests": nreq, "rhs": rhs, "offered_load": args.load, "arrival_rate_per_s": lam,
+        "served_p50_ms": 1e3 * percentile(lat, 50), "served_p99_ms": 1e3 * percentile(lat, 99),
+        "requests_per_s": nreq / wall,
+        "fifo_capacity_rhs_per_s": rhs / fifo_total,
+        "fifo_p50_ms": 1e3 * percentile(fifo_lat, 50), "fifo_p99_ms": 1e3 * percentile(fifo_lat, 99),
+        "failed_requests": bad, "rejected": len(sch.rejected),
+        "config": {"lattices": sizes, "gauge_fields_per_size": 2, "nslots": 12, "step_iters": args.step_iters,
+                   "precision": "mixed_fp32", "latency": "arrival to solution in device memory"},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path (see the design notes on "
               "how the lattice would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        print(json.dumps(run_serving(args)), flush=True)
+        return
     import numpy as np
     import torch
 

@@ -224,11 +224,9 @@ int wilson_gauge_free(wilson_ctx *ctx, wilson_gauge *g) {
     API_BEGIN
     WL_CHECK_ARG(ctx != nullptr && g != nullptr, "ctx / g is NULL");
     WL_HIP(hipStreamSynchronize(ctx->stream));
-    // cached workspaces may refer to this field
+    // the dslash workspace key names this field; solve workspaces take the field per call
     ctx->dslash_ws.reset();
-    ctx->solve_ws.reset();
     ctx->dslash_key.clear();
-    ctx->solve_key.clear();
     delete g;
     return WILSON_OK;
     API_END
@@ -331,12 +329,9 @@ int wilson_solve(double *x, const double *b, const double *U, double kappa, cons
         sx.copy_out();
         WL_HIP(hipStreamSynchronize(ctx->stream));
     } catch (...) {
-        ctx->solve_ws.reset();
         delete G;
         throw;
     }
-    ctx->solve_ws.reset();
-    ctx->solve_key.clear();
     delete G;
     return st;
     API_END

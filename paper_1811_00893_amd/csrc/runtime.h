@@ -124,9 +124,10 @@ struct wilson_ctx {
     wl::DevBuf stage_in, stage_out;  // canonical staging for host pointers
     wl::DevBuf flag;                 // device int for finiteness checks
     wl::PinnedBuf pinned;            // small host mirror
-    // cached workspaces of the last dslash / solve shape (reused across calls)
-    std::shared_ptr<void> dslash_ws, solve_ws;
-    std::string dslash_key, solve_key;
+    // cached workspaces: the last dslash shape, and up to 4 solve shapes (LRU)
+    std::shared_ptr<void> dslash_ws;
+    std::string dslash_key;
+    std::vector<std::pair<std::string, std::shared_ptr<void>>> solve_cache;
     void *stage(wl::DevBuf &b, size_t bytes);
 };
 

@@ -88,6 +88,11 @@ class EoCore {
         for (auto &e : ring_ev)
             if (e) (void)hipEventDestroy(e);
     }
+    // use another gauge field of the same shape
+    void bind(const wilson_gauge *gauge) {
+        if (!gauge->links(GP)) throw Error(WILSON_INVALID_ARG, "gauge field lacks the link precision requested");
+        G = gauge;
+    }
 
     size_t footprint() const {
         size_t b = 0;
@@ -376,20 +381,36 @@ class EoCore {
     }
 };
 
-static std::string solve_key(const wilson_gauge *G, int nrhs, const SolveParams &p) {
+static std::string solve_key(const wilson_gauge *G, const SolveParams &p) {
     std::ostringstream os;
-    os << (const void *)G << " " << nrhs << " " << p.precision << " " << p.method;
+    os << G->dims[0] << "x" << G->dims[1] << "x" << G->dims[2] << "x" << G->dims[3] << " " << p.precision << " "
+       << p.method;
     return os.str();
 }
 
+// Workspaces depend on the lattice shape, precision and method only (the gauge field is
+// bound per call); a cached one with room for at least nrhs right-hand sides is reused.
 static std::shared_ptr<EoCore> get_core(wilson_ctx *ctx, const wilson_gauge *G, int nrhs, const SolveParams &p) {
-    const std::string key = solve_key(G, nrhs, p);
-    if (ctx->solve_ws && ctx->solve_key == key) return std::static_pointer_cast<EoCore>(ctx->solve_ws);
-    ctx->solve_ws.reset();
+    const std::string key = solve_key(G, p);
+    auto &cache = ctx->solve_cache;
+    for (size_t k = 0; k < cache.size(); k++) {
+        if (cache[k].first != key) continue;
+        auto core = std::static_pointer_cast<EoCore>(cache[k].second);
+        if (core->nrhs >= nrhs) {
+            auto hit = cache[k];
+            cache.erase(cache.begin() + k);
+            cache.push_back(hit);  // most recently used last
+            core->bind(G);
+            return core;
+        }
+        WL_HIP(hipStreamSynchronize(ctx->stream));
+        cache.erase(cache.begin() + k);
+        break;
+    }
     WL_HIP(hipStreamSynchronize(ctx->stream));
+    if (cache.size() >= 4) cache.erase(cache.begin());
     auto core = std::make_shared<EoCore>(ctx, G, nrhs, p.precision, p.method);
-    ctx->solve_ws = core;
-    ctx->solve_key = key;
+    cache.emplace_back(key, core);
     return core;
 }
 
@@ -410,8 +431,9 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
     auto core = get_core(ctx, G, nrhs, prm);
     EoCore &C = *core;
     const Geom &g = C.g;
-    C.select_all();
-    C.kappa.assign(kappa, kappa + nrhs);
+    C.select(0, nrhs);
+    C.kappa.assign(C.nrhs, 0.0);
+    std::copy(kappa, kappa + nrhs, C.kappa.begin());
 
     // b -> parity fields; |b|^2
     WL_HIP(launch_to_parity(C.b_e.f, b_canon, g, 0, nrhs, 1.0, ctx->stream));

@@ -1,0 +1,112 @@
+"""Serving on the GPU: continuous batching through the library's batch API.
+
+Every finished right-hand side must pass the oracle's FP64 residual check, and a
+request's result must be the same alone and in a mix with other requests (within the
+tolerance; on these lattices the launch configuration is fixed, so it is bitwise).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_00893_amd import inputs
+from paper_1811_00893_amd.serve import Request, make_server
+
+pytestmark = pytest.mark.gpu
+
+
+def residual(x, b, U, k, dims):
+    return float(np.linalg.norm(b - oracle.apply_D(x, U, k, dims)) / np.linalg.norm(b))
+
+
+GAUGES = {"a": ((4, 4, 4, 4), 1101, 0.25), "b": ((4, 4, 2, 8), 1102, 0.35)}
+
+
+def fields():
+    return {gid: inputs.gauge_field(d, eps=e, seed=s) for gid, (d, s, e) in GAUGES.items()}
+
+
+def serve(requests, U, precision, nslots=4, step_iters=3):
+    sch, eng = make_server(hbm_budget=64e9, nslots=nslots, step_iters=step_iters, precision=precision)
+    try:
+        for gid, (dims, _, _) in GAUGES.items():
+            nb = eng.load_gauge(gid, U[gid].cuda(), dims)
+            sch.register_gauge(gid, dims, nb)
+        for r in requests:
+            assert sch.submit(r)
+        sch.run_until_idle()
+    finally:
+        sch.close()
+        eng.close()
+    return sch
+
+
+def make_requests(ids, seed0=0):
+    out = []
+    rng = np.random.default_rng(seed0)
+    for rid in ids:
+        gid = "a" if rid % 2 == 0 else "b"
+        dims = GAUGES[gid][0]
+        nrhs = 1 + rid % 3
+        b = inputs.gaussian_source(dims, seed=5000 + rid, nrhs=nrhs)
+        out.append(Request(rid=rid, gauge_id=gid, kappa=0.115 + 0.002 * (rid % 5), tol=[1e-8, 1e-10, 1e-12][rid % 3],
+                           b=b, maxiter=5000))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_serving_results_pass_oracle_and_match_alone(precision):
+    U = fields()
+    mix = make_requests(range(7))
+    sch = serve(mix, U, precision)
+    assert len(sch.completed) == 7
+    for r in sch.completed:
+        dims = GAUGES[r.gauge_id][0]
+        for j in range(r.nrhs):
+            assert r.status[j] == 0, (r.rid, j, r.status)
+            res = residual(r.x[j].numpy(), r.b[j].numpy(), U[r.gauge_id].numpy(), r.kappa, dims)
+            assert res < r.tol, (r.rid, j, res, r.tol)
+        assert r.latency > 0
+    # the same request alone
+    target = [r for r in sch.completed if r.rid == 4][0]
+    alone = serve(make_requests([4]), U, precision)
+    x_alone = alone.completed[0].x
+    d = float((x_alone - target.x).abs().max() / target.x.abs().max())
+    print(f"precision {precision}: alone vs mixed max relative difference {d:.2e}")
+    assert d < 10 * target.tol
+
+
+def test_batch_api_slot_lifecycle():
+    """attach -> step -> poll -> detach through the raw API; a busy slot refuses a second
+    attach, an unfinished slot refuses detach, and a freed slot is reusable."""
+    from paper_1811_00893_amd import _lib as L
+    dims = (4, 4, 4, 4)
+    U = inputs.gauge_field(dims, seed=1201)
+    ctx = L.wilson_context_create()
+    g = L.wilson_gauge_load(ctx, U.cuda(), dims)
+    bat = L.wilson_batch_create(ctx, g, 2, {"precision": 0})
+    b0 = inputs.gaussian_source(dims, seed=1)
+    b1 = inputs.gaussian_source(dims, seed=2)
+    assert L.wilson_batch_attach(bat, 0, b0, 0.12, 1e-10) == 0
+    assert L.wilson_batch_attach(bat, 0, b1, 0.12, 1e-10) == L.WILSON_BUSY
+    x = torch.zeros_like(b0)
+    st, _ = L.wilson_batch_detach(bat, 0, x)
+    assert st == L.WILSON_BUSY
+    assert L.wilson_batch_attach(bat, 1, b1, 0.125, 1e-10) == 0
+    for _ in range(200):
+        L.wilson_batch_step(bat, 4)
+        state, status = L.wilson_batch_poll(bat, 2)
+        if (state == 2).all():
+            break
+    assert (state == 2).all() and (status == 0).all()
+    for slot, (b, k) in enumerate(((b0, 0.12), (b1, 0.125))):
+        x = torch.zeros_like(b)
+        st, info = L.wilson_batch_detach(bat, slot, x)
+        assert st == 0 and info["converged"] == 1
+        assert residual(x.numpy(), b.numpy(), U.numpy(), k, dims) < 1e-10
+    state, _ = L.wilson_batch_poll(bat, 2)
+    assert (state == 0).all()
+    assert L.wilson_batch_attach(bat, 0, b1, 0.125, 1e-10) == 0  # reusable
+    L.wilson_batch_destroy(bat)
+    L.wilson_gauge_free(ctx, g)
+    L.wilson_context_destroy(ctx)
