@@ -41,6 +41,31 @@ def parse():
     return p.parse_args()
 
 
+KERNEL_SOURCES = ["paper_1811_00893_amd/csrc/dslash.hip", "paper_1811_00893_amd/csrc/device.h",
+                  "paper_1811_00893_amd/csrc/common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload, dslash):
+    """HBM bytes per hop launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on the library's streaming copy), or None when the kernel
+    sources changed since the counters were taken or no summary covers this workload."""
+    path = os.path.join(ROOT, "profiles", "hop_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload)
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def percentile(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v), q))
@@ -55,6 +80,8 @@ WORKLOADS = {
                 "mixed precision (FP32 inner, FP64 outer) even-odd BiCGStab, 48^3x96, kappa=0.125, tol=1e-10"),
     "mixed48_fp16": ((48, 48, 48, 96), 0.125, 1e-10, 3, 1,
                      "mixed precision (FP16 spinors + per-site scale, FP32 links inner; FP64 outer), 48^3x96"),
+    "mixed48_fp16h": ((48, 48, 48, 96), 0.125, 1e-10, 2, 1,
+                      "mixed precision (FP16 spinors + per-site scale, FP16 links inner; FP64 outer), 48^3x96"),
     "batched24": ((24, 24, 24, 48), 0.125, 1e-10, 1, 12,
                   "12 point sources in one batched solve, FP32 inner / FP64 outer, 24^3x48, kappa=0.125"),
 }
@@ -207,30 +234,32 @@ def main():
     opts = {"precision": precision, "maxiter": 20000}
 
     # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload) ----
-    dprec = 0 if precision == 0 else 1
-    psi = srcs[0] if nrhs == 1 else srcs[0][0].contiguous()
+    dprec = precision  # the workload's inner precision
+    psi = srcs[0]  # all right-hand sides of the workload in one launch
     out = torch.zeros_like(psi)
     for _ in range(3):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec), "dslash")
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec, nrhs), "dslash")
     torch.cuda.synchronize()
     L.wilson_timing_enable(ctx, True)
     for _ in range(args.dslash_reps):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec), "dslash")
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec, nrhs), "dslash")
     torch.cuda.synchronize()
     d_ms, d_n, d_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
     L.wilson_timing_enable(ctx, False)
     d_us = 1e3 * d_ms / max(d_n, 1)
     d_gbs = d_bytes / (d_ms * 1e-3) / 1e9
-    sname = "fp64" if dprec == 0 else "fp32"
+    sname = {0: "fp64", 1: "fp32", 2: "fp16", 3: "fp16"}[dprec]
+    lname = {0: "fp64", 1: "fp32", 2: "fp16", 3: "fp32"}[dprec]
     dslash = {
         "precision": sname,
+        "nrhs": nrhs,
         "us_per_launch": d_us,
         "launches": d_n,
         "algorithmic_bytes_per_launch": d_bytes / max(d_n, 1),
-        "bytes_per_site": counts.hop_bytes_per_site(sname),
+        "bytes_per_site": 8 * counts.link_bytes(lname) + nrhs * 2 * counts.spinor_site_bytes(sname),
         "gbs": d_gbs,
         "frac_hbm_peak": d_gbs / counts.MI355X_HBM_GBS,
-        "gflops": counts.HOP_FLOPS_PER_SITE * Vh / (d_us * 1e-6) / 1e9,
+        "gflops": counts.HOP_FLOPS_PER_SITE * Vh * nrhs / (d_us * 1e-6) / 1e9,
         "working_set_mb": d_bytes / max(d_n, 1) / 1e6,
     }
 
@@ -288,21 +317,45 @@ def main():
     L.wilson_timing_enable(ctx, False)
     solves = args.steps * nrhs
     hop_gbs = h_bytes / (h_ms * 1e-3) / 1e9
+    traffic = committed_traffic(args.workload, dslash)
     roofline = {
         "bound": "hbm",
-        "kernel": "parity hop (all hop launches of the timed solves)",
-        "achieved": hop_gbs,
+        "kernel": f"parity hop (Dslash D_eo = -kappa H_eo), {sname} spinors, {nrhs} RHS, {list(dims)}",
+        "achieved": d_gbs,
         "peak": counts.MI355X_HBM_GBS,
         "unit": "GB/s",
-        "frac": hop_gbs / counts.MI355X_HBM_GBS,
-        "frac_of_copy_bw": hop_gbs / copy_gbs,
-        "traffic": None,
+        "frac": d_gbs / counts.MI355X_HBM_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": dslash["algorithmic_bytes_per_launch"],
+        "us_per_launch": d_us,
+        "frac_of_copy_bw": d_gbs / copy_gbs,
+        "frac_of_read_bw": d_gbs / read_gbs,
+    }
+    solve_hops = {
         "launches": h_n,
         "us_per_launch": 1e3 * h_ms / max(h_n, 1),
-        "algorithmic_bytes_per_launch": h_bytes / max(h_n, 1),
+        "algorithmic_gbs": hop_gbs,
+        "frac_hbm_peak": hop_gbs / counts.MI355X_HBM_GBS,
         "hop_time_fraction": h_ms / (total * 1e3),
         "blas_gbs": b_bytes / (b_ms * 1e-3) / 1e9 if b_ms > 0 else None,
+        "blas_time_fraction": b_ms / (total * 1e3),
     }
+
+    # ---- batched workloads: the same right-hand sides solved one at a time ----
+    sequential = None
+    if nrhs > 1:
+        seq_t = []
+        for i in range(min(args.steps, 3)):
+            s0 = time.perf_counter()
+            for k in range(nrhs):
+                xk = torch.zeros_like(srcs[0][k])
+                st, _ = L.wilson_solve_ex(ctx, g, xk, srcs[0][k].contiguous(), 1, kappa, tol, opts)
+                L.check(st, "sequential solve")
+            torch.cuda.synchronize()
+            seq_t.append(time.perf_counter() - s0)
+        sequential = {"value": nrhs / float(np.median(seq_t)), "unit": "solves/s",
+                      "ms_per_batch": 1e3 * float(np.median(seq_t)),
+                      "speedup_of_batched": (solves / total) / (nrhs / float(np.median(seq_t)))}
 
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
@@ -356,7 +409,9 @@ def main():
         "true_residual_max": max(res),
         "dslash": dslash,
         "roofline": roofline,
+        "solve_hops": solve_hops,
         "cpu_baseline": cpu,
+        "sequential_single_rhs": sequential,
         "hbm_copy_gbs": copy_gbs,
         "hbm_read_gbs": read_gbs,
         "setup_s": setup_s,

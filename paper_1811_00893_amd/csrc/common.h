@@ -3,13 +3,15 @@
 // Data layout in HBM ("parity-split structure of arrays"):
 //   * a lattice site (x,y,z,t) of parity p = (x+y+z+t)&1 has checkerboard index
 //     cb = (x + Lx*(y + Ly*(z + Lz*t))) / 2 in [0, Vh), Vh = V/2;
-//   * a spinor field of one parity is 12 complex "planes" (component c = 3*spin + colour),
-//     plane c holds that component for every cb site: element (c, cb) at [c*stride + cb];
-//     nrhs fields are stacked with rhs stride 12*stride elements.  FP16 fields add one
-//     FP32 scale per site, [rhs*stride + cb];
-//   * links: plane (p, mu, e=3a+b) holds U_mu(x)[a][b] of every parity-p site x:
-//     element [((p*4 + mu)*9 + e)*stride + cb]; the antiperiodic sign is folded into
-//     U_t on the t = Lt-1 slice.
+//   * a spinor field of one parity is a set of planes of 16-byte elements; element plane e
+//     holds components CPE*e .. CPE*e+CPE-1 (component c = 3*spin + colour; CPE = 1, 2, 4
+//     complex for FP64, FP32, FP16) of every cb site: element (e, cb) at byte
+//     (e*stride + cb)*16; nrhs fields are stacked with 12/CPE planes each.  FP16 fields add
+//     one FP32 scale per site, [rhs*stride + cb];
+//   * links: element plane (p, mu, e) holds entries of U_mu(x) of every parity-p site x
+//     (row-major entries, 1 complex per 16-byte FP64 element, 2 per FP32 / FP16 element);
+//     SU(3) fields keep rows 0 and 1 only, other fields all 9 entries with the
+//     antiperiodic sign folded into U_t on the t = Lt-1 slice.
 // One lane processes one site: every plane load of a wavefront is one contiguous,
 // fully coalesced segment.
 #pragma once
@@ -116,6 +118,7 @@ struct LaunchCfg {
     int rpt = 1;       // right-hand sides per thread (multi-RHS hop)
     int xcd = 1;       // XCD-contiguous tile order
     int zblk = 0;      // >0: visit (z,t) planes in blocks of zblk z-values, t inner (divides Lz)
+    int lds_kb = 0;    // >0: reserve this much LDS per block to cap blocks per CU (waves in flight)
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----
@@ -165,8 +168,12 @@ hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geo
 // Sets *flag (device int) to 1 if any canonical link deviates from SU(3) by more than tol
 // (max |U U^dag - 1|, |det U - 1|).
 hipError_t launch_su3_check(const double *canon, size_t nlinks, double tol, int *flag, hipStream_t s);
+// Link planes: 16-byte elements of 1 (FP64) or 2 (FP32) complex, 8-byte elements of 2
+// complex (FP16); 6 or 9 complex entries per link.
 inline size_t gauge_bytes(int prec, int recon, const Geom &g) {
-    return (size_t)2 * 4 * (recon == 12 ? 6 : 9) * g.stride * 2 * real_bytes(prec);
+    const int ne = recon == 12 ? 6 : 9;
+    const int nl = prec == P64 ? ne : (ne + 1) / 2;
+    return (size_t)2 * 4 * nl * g.stride * (prec == P16 ? 8 : 16);
 }
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Read-only bandwidth probe; sink needs 8192 unsigned words.

@@ -53,110 +53,130 @@ __device__ __forceinline__ Cx<R> cfma_conj(Cx<R> acc, Cx<R> a, Cx<R> b) {
 template <int P>
 using real_t = typename std::conditional<P == P64, double, float>::type;
 
-// ---- storage access: one complex number at element index idx of a plane array ----
-template <int P, typename R>
-__device__ __forceinline__ Cx<R> ld_c(const void *base, size_t idx) {
-    if constexpr (P == P64) {
-        double2 v = reinterpret_cast<const double2 *>(base)[idx];
-        return {(R)v.x, (R)v.y};
-    } else if constexpr (P == P32) {
-        float2 v = reinterpret_cast<const float2 *>(base)[idx];
-        return {(R)v.x, (R)v.y};
-    } else {
-        half2_t v = reinterpret_cast<const half2_t *>(base)[idx];
-        return {(R)(float)v.x, (R)(float)v.y};
-    }
-}
+// ---- storage: packed 16-byte plane elements ------------------------------------------
+// Spinor planes hold 16-byte elements: 1 complex (FP64), 2 (FP32) or 4 (FP16) consecutive
+// components, so every lane moves 16 bytes per load in every precision (narrower loads
+// would make the per-CU load units, not HBM, the limit).  Component c of a site lives in
+// element plane c / CPE, slot c % CPE; a field of one parity has NEL = 12 / CPE planes
+// per right-hand side.  Links use 16-byte elements of 1 (FP64) or 2 (FP32) complex and
+// 8-byte elements of 2 complex (FP16).
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef _Float16 hvec4 __attribute__((ext_vector_type(4)));
+typedef _Float16 hvec8 __attribute__((ext_vector_type(8)));
 
-// Streaming (read-once) variant for links: non-temporal so they do not evict spinors.
-template <int P, typename R>
-__device__ __forceinline__ Cx<R> ld_c_nt(const void *base, size_t idx) {
-    if constexpr (P == P64) {
-        const dvec2 *p = reinterpret_cast<const dvec2 *>(base) + idx;
-        dvec2 v = __builtin_nontemporal_load(p);
-        return {(R)v.x, (R)v.y};
-    } else if constexpr (P == P32) {
-        const fvec2 *p = reinterpret_cast<const fvec2 *>(base) + idx;
-        fvec2 v = __builtin_nontemporal_load(p);
-        return {(R)v.x, (R)v.y};
-    } else {
-        const half2_t *p = reinterpret_cast<const half2_t *>(base) + idx;
-        half2_t v = __builtin_nontemporal_load(p);
-        return {(R)(float)v.x, (R)(float)v.y};
-    }
-}
-
-template <int P, typename R>
-__device__ __forceinline__ void st_c(void *base, size_t idx, Cx<R> v) {
-    if constexpr (P == P64) {
-        reinterpret_cast<double2 *>(base)[idx] = make_double2((double)v.re, (double)v.im);
-    } else if constexpr (P == P32) {
-        reinterpret_cast<float2 *>(base)[idx] = make_float2((float)v.re, (float)v.im);
-    } else {
-        half2_t h;
-        h.x = (_Float16)(float)v.re;
-        h.y = (_Float16)(float)v.im;
-        reinterpret_cast<half2_t *>(base)[idx] = h;
-    }
-}
-
-// ---- plane addressing: a wave-uniform plane base plus one 32-bit per-lane byte offset,
-// so that every plane load of a site shares the same offset register and the base
-// stays in scalar registers ----
 template <int P>
-struct Elem {
-    static constexpr unsigned bytes = P == P64 ? 16u : (P == P32 ? 8u : 4u);
+struct SpinorPack {
+    static constexpr int CPE = P == P64 ? 1 : (P == P32 ? 2 : 4);  // complex per element
+    static constexpr int NEL = 12 / CPE;                            // elements per site
 };
 template <int P>
-__device__ __forceinline__ const char *plane_ptr(const void *base, int plane, int stride) {
-    return static_cast<const char *>(base) + (size_t)plane * stride * Elem<P>::bytes;
+struct LinkPack {
+    static constexpr int CPL = P == P64 ? 1 : 2;          // complex per element
+    static constexpr unsigned EB = P == P16 ? 8u : 16u;  // element bytes
+};
+template <int P, int NE>
+struct LinkElems {
+    static constexpr int N = (NE + LinkPack<P>::CPL - 1) / LinkPack<P>::CPL;
+};
+__host__ __device__ constexpr int link_elems(int prec, int ne) { return prec == P64 ? ne : (ne + 1) / 2; }
+__host__ __device__ constexpr unsigned link_elem_bytes(int prec) { return prec == P16 ? 8u : 16u; }
+
+// plane addressing: a wave-uniform plane base plus one 32-bit per-lane byte offset, so the
+// loads of a site share one offset register and the bases stay in scalar registers
+__device__ __forceinline__ const char *splane(const void *base, int plane, int stride) {
+    return static_cast<const char *>(base) + (size_t)plane * stride * 16u;
 }
+template <int P>
+__device__ __forceinline__ const char *lplane(const void *base, int plane, int stride) {
+    return static_cast<const char *>(base) + (size_t)plane * stride * LinkPack<P>::EB;
+}
+
 template <int P, typename R>
-__device__ __forceinline__ Cx<R> ld_p(const char *plane, unsigned off) {
+__device__ __forceinline__ void ld_elem(Cx<R> *o, const char *plane, unsigned off) {
     if constexpr (P == P64) {
-        double2 v = *reinterpret_cast<const double2 *>(plane + off);
-        return {(R)v.x, (R)v.y};
+        const dvec2 v = *reinterpret_cast<const dvec2 *>(plane + off);
+        o[0] = {(R)v.x, (R)v.y};
     } else if constexpr (P == P32) {
-        float2 v = *reinterpret_cast<const float2 *>(plane + off);
-        return {(R)v.x, (R)v.y};
+        const fvec4 v = *reinterpret_cast<const fvec4 *>(plane + off);
+        o[0] = {(R)v.x, (R)v.y};
+        o[1] = {(R)v.z, (R)v.w};
     } else {
-        half2_t v = *reinterpret_cast<const half2_t *>(plane + off);
-        return {(R)(float)v.x, (R)(float)v.y};
+        const hvec8 v = *reinterpret_cast<const hvec8 *>(plane + off);
+#pragma unroll
+        for (int k = 0; k < 4; k++) o[k] = {(R)(float)v[2 * k], (R)(float)v[2 * k + 1]};
     }
 }
 template <int P, typename R>
-__device__ __forceinline__ Cx<R> ld_p_nt(const char *plane, unsigned off) {
+__device__ __forceinline__ void st_elem(char *plane, unsigned off, const Cx<R> *x) {
     if constexpr (P == P64) {
-        dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(plane + off));
-        return {(R)v.x, (R)v.y};
+        dvec2 v;
+        v.x = (double)x[0].re;
+        v.y = (double)x[0].im;
+        *reinterpret_cast<dvec2 *>(plane + off) = v;
     } else if constexpr (P == P32) {
-        fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2 *>(plane + off));
-        return {(R)v.x, (R)v.y};
+        fvec4 v;
+        v.x = (float)x[0].re;
+        v.y = (float)x[0].im;
+        v.z = (float)x[1].re;
+        v.w = (float)x[1].im;
+        *reinterpret_cast<fvec4 *>(plane + off) = v;
     } else {
-        half2_t v = __builtin_nontemporal_load(reinterpret_cast<const half2_t *>(plane + off));
-        return {(R)(float)v.x, (R)(float)v.y};
+        hvec8 v;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            v[2 * k] = (_Float16)(float)x[k].re;
+            v[2 * k + 1] = (_Float16)(float)x[k].im;
+        }
+        *reinterpret_cast<hvec8 *>(plane + off) = v;
+    }
+}
+// link element (non-temporal: links are read once per hop and should not evict spinors)
+template <int P, typename R>
+__device__ __forceinline__ void ld_link_elem(Cx<R> *o, const char *plane, unsigned off) {
+    if constexpr (P == P64) {
+        const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(plane + off));
+        o[0] = {(R)v.x, (R)v.y};
+    } else if constexpr (P == P32) {
+        const fvec4 v = __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(plane + off));
+        o[0] = {(R)v.x, (R)v.y};
+        o[1] = {(R)v.z, (R)v.w};
+    } else {
+        const hvec4 v = __builtin_nontemporal_load(reinterpret_cast<const hvec4 *>(plane + off));
+        o[0] = {(R)(float)v[0], (R)(float)v[1]};
+        o[1] = {(R)(float)v[2], (R)(float)v[3]};
     }
 }
 template <int P, typename R>
-__device__ __forceinline__ void st_p(char *plane, unsigned off, Cx<R> v) {
+__device__ __forceinline__ void st_link_elem(char *plane, unsigned off, const Cx<R> *x) {
     if constexpr (P == P64) {
-        *reinterpret_cast<double2 *>(plane + off) = make_double2((double)v.re, (double)v.im);
+        dvec2 v;
+        v.x = (double)x[0].re;
+        v.y = (double)x[0].im;
+        *reinterpret_cast<dvec2 *>(plane + off) = v;
     } else if constexpr (P == P32) {
-        *reinterpret_cast<float2 *>(plane + off) = make_float2((float)v.re, (float)v.im);
+        fvec4 v;
+        v.x = (float)x[0].re;
+        v.y = (float)x[0].im;
+        v.z = (float)x[1].re;
+        v.w = (float)x[1].im;
+        *reinterpret_cast<fvec4 *>(plane + off) = v;
     } else {
-        half2_t h;
-        h.x = (_Float16)(float)v.re;
-        h.y = (_Float16)(float)v.im;
-        *reinterpret_cast<half2_t *>(plane + off) = h;
+        hvec4 v;
+        v[0] = (_Float16)(float)x[0].re;
+        v[1] = (_Float16)(float)x[0].im;
+        v[2] = (_Float16)(float)x[1].re;
+        v[3] = (_Float16)(float)x[1].im;
+        *reinterpret_cast<hvec4 *>(plane + off) = v;
     }
 }
 
 // Full site (12 complex) of rhs `r` of a parity field; FP16 values are rescaled.
 template <int P, typename R>
 __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int stride, int r, int i) {
-    const unsigned off = (unsigned)i * Elem<P>::bytes;
+    constexpr int CPE = SpinorPack<P>::CPE, NEL = SpinorPack<P>::NEL;
+    const unsigned off = (unsigned)i * 16u;
 #pragma unroll
-    for (int c = 0; c < 12; c++) v[c] = ld_p<P, R>(plane_ptr<P>(f.data, r * 12 + c, stride), off);
+    for (int e = 0; e < NEL; e++) ld_elem<P, R>(&v[e * CPE], splane(f.data, r * NEL + e, stride), off);
     if constexpr (P == P16) {
         const R s = (R)f.scale[(size_t)r * stride + i];
 #pragma unroll
@@ -167,29 +187,25 @@ __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int s
 // FP16 encoding of a site: s = max |component| (FP32), h = fp16_rne(fp32(v / s)), s = 0 -> zeros.
 template <int P, typename R>
 __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, int i, const Cx<R> (&v)[12]) {
-    const unsigned off = (unsigned)i * Elem<P>::bytes;
+    constexpr int CPE = SpinorPack<P>::CPE, NEL = SpinorPack<P>::NEL;
+    const unsigned off = (unsigned)i * 16u;
     if constexpr (P == P16) {
-        float vf[24];
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-            vf[2 * c] = (float)v[c].re;
-            vf[2 * c + 1] = (float)v[c].im;
-        }
         float s = 0.f;
 #pragma unroll
-        for (int k = 0; k < 24; k++) s = fmaxf(s, fabsf(vf[k]));
+        for (int c = 0; c < 12; c++) s = fmaxf(s, fmaxf(fabsf((float)v[c].re), fabsf((float)v[c].im)));
         const float sd = s > 0.f ? s : 1.f;
+        Cx<float> q[12];
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            half2_t h;
-            h.x = (_Float16)(s > 0.f ? vf[2 * c] / sd : 0.f);
-            h.y = (_Float16)(s > 0.f ? vf[2 * c + 1] / sd : 0.f);
-            *reinterpret_cast<half2_t *>(const_cast<char *>(plane_ptr<P>(f.data, r * 12 + c, stride)) + off) = h;
-        }
+        for (int c = 0; c < 12; c++)
+            q[c] = s > 0.f ? Cx<float>{(float)v[c].re / sd, (float)v[c].im / sd} : Cx<float>{0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < NEL; e++)
+            st_elem<P, float>(const_cast<char *>(splane(f.data, r * NEL + e, stride)), off, &q[e * CPE]);
         f.scale[(size_t)r * stride + i] = s;
     } else {
 #pragma unroll
-        for (int c = 0; c < 12; c++) st_p<P, R>(const_cast<char *>(plane_ptr<P>(f.data, r * 12 + c, stride)), off, v[c]);
+        for (int e = 0; e < NEL; e++)
+            st_elem<P, R>(const_cast<char *>(splane(f.data, r * NEL + e, stride)), off, &v[e * CPE]);
     }
 }
 

@@ -106,13 +106,20 @@ __global__ void __launch_bounds__(256) gauge_pack_kernel(void *dst, const double
     int t;
     const int s = full_site(g, i, par, &t);
     const int ne = recon == 12 ? 6 : 9;
+    const int nl = link_elems(P, ne);
+    constexpr int CPL = LinkPack<P>::CPL;
     const double sgn = (recon == 18 && mu == 3 && t == g.L[3] - 1) ? -1.0 : 1.0;
     const double2 *src = canon + ((size_t)s * 4 + mu) * 9;
     using R = real_t<P>;
-    const size_t base = (size_t)((par * 4 + mu) * ne) * g.stride + i;
-    for (int e = 0; e < ne; e++) {
-        const double2 d = src[e];
-        st_c<P, R>(dst, base + (size_t)e * g.stride, Cx<R>{(R)(sgn * d.x), (R)(sgn * d.y)});
+    const unsigned off = (unsigned)i * LinkPack<P>::EB;
+    for (int e = 0; e < nl; e++) {
+        Cx<R> x[CPL];
+        for (int k = 0; k < CPL; k++) {
+            const int idx = e * CPL + k;  // entries past the last are padding
+            const double2 d = idx < ne ? src[idx] : make_double2(0.0, 0.0);
+            x[k] = {(R)(sgn * d.x), (R)(sgn * d.y)};
+        }
+        st_link_elem<P, R>(const_cast<char *>(lplane<P>(dst, (par * 4 + mu) * nl + e, g.stride)), off, x);
     }
 }
 

@@ -136,8 +136,10 @@ void wilson_ctx::load_tune_cache() {
     const char *env = std::getenv("WILSON_TUNE");
     if (env && std::strcmp(env, "0") == 0) tune_enabled = false;
     const char *fc = std::getenv("WILSON_HOP_CFG");
-    if (fc && std::sscanf(fc, "%d,%d,%d,%d", &forced_cfg.block, &forced_cfg.rpt, &forced_cfg.xcd, &forced_cfg.zblk) == 4)
-        forced = true;
+    if (fc) {
+        forced = std::sscanf(fc, "%d,%d,%d,%d,%d", &forced_cfg.block, &forced_cfg.rpt, &forced_cfg.xcd,
+                             &forced_cfg.zblk, &forced_cfg.lds_kb) >= 4;
+    }
     const char *path = std::getenv("WILSON_TUNE_CACHE");
     if (!path || !*path) return;
     tune_path = path;
@@ -151,8 +153,8 @@ void wilson_ctx::load_tune_cache() {
         if (k1 == std::string::npos) continue;
         const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
         LaunchCfg c;
-        if (std::sscanf(line.c_str() + k1, "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d", &c.block,
-                        &c.rpt, &c.xcd, &c.zblk) == 4)
+        if (std::sscanf(line.c_str() + k1, "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d",
+                        &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb) == 5)
             tuned[key] = c;
     }
 }
@@ -161,7 +163,7 @@ void wilson_ctx::save_tune_entry(const std::string &key, const LaunchCfg &c, dou
     if (tune_path.empty()) return;
     std::ofstream out(tune_path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
-        << ", \"zblk\": " << c.zblk << ", \"ms\": " << ms << "}\n";
+        << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"ms\": " << ms << "}\n";
 }
 
 namespace wl {
@@ -190,15 +192,17 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
     for (int block : {64, 128, 256})
         for (int rpt : {1, 2, 3, 4})
             for (int xcd : {0, 1})
-                for (int zblk : {0, 2, 4, 8}) {
-                    if (xcd == 0 && zblk != 0) continue;  // plane blocking only matters per XCD
-                    LaunchCfg c;
-                    c.block = block;
-                    c.rpt = rpt;
-                    c.xcd = xcd;
-                    c.zblk = zblk;
-                    if (hop_cfg_valid(a, c)) cands.push_back(c);
-                }
+                for (int zblk : {0, 4, 8})
+                    for (int lds_kb : {0, 24, 40, 56}) {
+                        if (xcd == 0 && (zblk != 0 || lds_kb != 0)) continue;
+                        LaunchCfg c;
+                        c.block = block;
+                        c.rpt = rpt;
+                        c.xcd = xcd;
+                        c.zblk = zblk;
+                        c.lds_kb = lds_kb;
+                        if (hop_cfg_valid(a, c)) cands.push_back(c);
+                    }
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
@@ -206,7 +210,10 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
     double bms = 1e30;
     const int reps = a.g.Vh >= (1 << 18) ? 3 : 10;
     for (const auto &c : cands) {
-        WL_HIP(launch_hop(a, c, ctx->stream));  // warm-up
+        if (launch_hop(a, c, ctx->stream) != hipSuccess) {  // warm-up; skip shapes that cannot launch
+            (void)hipGetLastError();
+            continue;
+        }
         WL_HIP(hipEventRecord(e0, ctx->stream));
         for (int r = 0; r < reps; r++) WL_HIP(launch_hop(a, c, ctx->stream));
         WL_HIP(hipEventRecord(e1, ctx->stream));
@@ -215,8 +222,8 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         WL_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
         if (std::getenv("WILSON_TUNE_VERBOSE"))
-            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d: %.2f us\n", hop_key(a).c_str(), c.block,
-                         c.rpt, c.xcd, c.zblk, per * 1e3);
+            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d: %.2f us\n", hop_key(a).c_str(),
+                         c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, per * 1e3);
         if (per < bms) {
             bms = per;
             best = c;

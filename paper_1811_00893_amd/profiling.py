@@ -1,0 +1,109 @@
+"""Summaries of rocprofv3 CSV output for the committed profile records.
+
+  stats   : kernel-trace statistics (`rocprofv3 --kernel-trace --stats --output-format csv`)
+            -> a short text table of the top kernels with the command that produced it.
+  traffic : HBM bytes per launch of the hop kernel from two counter runs
+            (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`; values in KiB per dispatch), each
+            calibrated by what the same counter reports for the library's streaming copy of
+            2 GiB in the same run (FETCH_SIZE reports half the bytes read on this part).
+
+Usage:
+  python -m paper_1811_00893_amd.profiling stats --dir D --out F --command "..."
+  python -m paper_1811_00893_amd.profiling traffic --workload W --fetch D1 --write D2 --out F --command "..."
+"""
+import argparse
+import csv
+import glob
+import json
+import os
+import sys
+
+COPY_BYTES = 1 << 31  # the probe in bench.py copies 2 GiB
+
+
+def _find(d, suffix):
+    hits = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def short_name(name):
+    n = name.replace("void ", "")
+    return n.split("(")[0][:70]
+
+
+def stats(d, out, command, top=14):
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'calls':>7} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
+    for r in rows[:top]:
+        lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.1f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.2f} {100 * float(r['TotalDurationNs']) / total:6.1f}  "
+                     f"{short_name(r['Name'])}")
+    text = "\n".join(lines) + "\n"
+    open(out, "w").write(text)
+    return text
+
+
+def _counter(d, kernel_substr):
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    kern = [float(r["Counter_Value"]) for r in rows if kernel_substr in r["Kernel_Name"]]
+    copy = [float(r["Counter_Value"]) for r in rows if "stream_copy_kernel" in r["Kernel_Name"]]
+    if not kern or not copy:
+        raise ValueError(f"{d}: kernel '{kernel_substr}' or the copy probe not found")
+    name = [r["Kernel_Name"] for r in rows if kernel_substr in r["Kernel_Name"]][0]
+    return sum(kern) / len(kern), len(kern), sum(copy) / len(copy), name
+
+
+def traffic(workload, fetch_dir, write_dir, out, command, kernel_substr="hop_kernel"):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench  # the hash of the kernel sources the counters describe
+    f_kib, nf, f_copy_kib, name = _counter(fetch_dir, kernel_substr)
+    w_kib, nw, w_copy_kib, _ = _counter(write_dir, kernel_substr)
+    f_scale = COPY_BYTES / (f_copy_kib * 1024)   # bytes read per FETCH_SIZE byte
+    w_scale = COPY_BYTES / (w_copy_kib * 1024)   # bytes written per WRITE_SIZE byte
+    rec = {
+        "kernel": short_name(name),
+        "dispatches": [nf, nw],
+        "fetch_kib_per_dispatch": f_kib,
+        "write_kib_per_dispatch": w_kib,
+        "copy_probe_fetch_kib": f_copy_kib,
+        "copy_probe_write_kib": w_copy_kib,
+        "fetch_scale": f_scale,
+        "write_scale": w_scale,
+        "fetch_bytes_per_launch": f_kib * 1024 * f_scale,
+        "write_bytes_per_launch": w_kib * 1024 * w_scale,
+        "kernel_source_hash": bench.kernel_source_hash(),
+        "command": command,
+    }
+    db = json.load(open(out)) if os.path.exists(out) else {}
+    db[workload] = rec
+    json.dump(db, open(out, "w"), indent=1, sort_keys=True)
+    return rec
+
+
+def main():
+    p = argparse.ArgumentParser()
+    sub = p.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("--dir", required=True)
+    a.add_argument("--out", required=True)
+    a.add_argument("--command", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--workload", required=True)
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--out", required=True)
+    b.add_argument("--command", required=True)
+    args = p.parse_args()
+    if args.cmd == "stats":
+        print(stats(args.dir, args.out, args.command))
+    else:
+        print(json.dumps(traffic(args.workload, args.fetch, args.write, args.out, args.command), indent=1))
+
+
+if __name__ == "__main__":
+    main()
