@@ -41,8 +41,8 @@ def parse():
     return p.parse_args()
 
 
-KERNEL_SOURCES = ["paper_1811_00893_amd/csrc/dslash.hip", "paper_1811_00893_amd/csrc/device.h",
-                  "paper_1811_00893_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_1811_00893_amd/csrc/dslash.hip", "paper_1811_00893_amd/csrc/dslash_kernels.h",
+                  "paper_1811_00893_amd/csrc/device.h", "paper_1811_00893_amd/csrc/common.h"]
 
 
 def kernel_source_hash():

@@ -28,12 +28,38 @@ enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };
 
 inline size_t real_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
+// Division of a non-negative 31-bit n by a fixed d >= 1 with one multiply-high, an add
+// and a shift (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// n / d = (mulhi(m, n) + n) >> l; mulhi + n stays below 2^32 because n < 2^31.
+struct FastDiv {
+    uint32_t d = 1, m = 1, l = 0;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while ((1ull << l) < d) l++;
+    f.l = l;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+    return f;
+}
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t hi = __umulhi(f.m, n);
+#else
+    const uint32_t hi = (uint32_t)(((uint64_t)f.m * n) >> 32);
+#endif
+    return (hi + n) >> f.l;
+}
+
 struct Geom {
     int L[4];     // Lx, Ly, Lz, Lt
     int Lxh;      // Lx / 2
     int Vh;       // sites per parity
     int stride;   // plane stride (Vh rounded up to a multiple of 64)
     int sy, sz, st;  // checkerboard-index strides of +y, +z, +t
+    FastDiv dLxh, dLy, dLz;  // division by Lx/2, Ly, Lz (site-index decoding)
 };
 
 Geom make_geom(const int32_t dims[4]);
@@ -119,6 +145,7 @@ struct LaunchCfg {
     int xcd = 1;       // XCD-contiguous tile order
     int zblk = 0;      // >0: visit (z,t) planes in blocks of zblk z-values, t inner (divides Lz)
     int lds_kb = 0;    // >0: reserve this much LDS per block to cap blocks per CU (waves in flight)
+    int wsplit = 0;    // 1: the waves of a block take successive RHS groups of the same 64 sites
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----

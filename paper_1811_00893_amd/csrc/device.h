@@ -83,12 +83,21 @@ __host__ __device__ constexpr unsigned link_elem_bytes(int prec) { return prec =
 
 // plane addressing: a wave-uniform plane base plus one 32-bit per-lane byte offset, so the
 // loads of a site share one offset register and the bases stay in scalar registers
+// The plane base is passed through readfirstlane: it is uniform anyway, and without it the
+// compiler folds the lane offset into the base first and then adds each plane's offset
+// with a 64-bit per-lane multiply-add, instead of one scalar base per plane.
+__device__ __forceinline__ const char *uniform_ptr(const char *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const char *>(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ const char *splane(const void *base, int plane, int stride) {
-    return static_cast<const char *>(base) + (size_t)plane * stride * 16u;
+    return uniform_ptr(static_cast<const char *>(base) + (size_t)plane * stride * 16u);
 }
 template <int P>
 __device__ __forceinline__ const char *lplane(const void *base, int plane, int stride) {
-    return static_cast<const char *>(base) + (size_t)plane * stride * LinkPack<P>::EB;
+    return uniform_ptr(static_cast<const char *>(base) + (size_t)plane * stride * LinkPack<P>::EB);
 }
 
 template <int P, typename R>
@@ -130,18 +139,25 @@ __device__ __forceinline__ void st_elem(char *plane, unsigned off, const Cx<R> *
         *reinterpret_cast<hvec8 *>(plane + off) = v;
     }
 }
-// link element (non-temporal: links are read once per hop and should not evict spinors)
-template <int P, typename R>
+// link element.  NT (non-temporal) when a launch reads each link once, so links do not
+// evict spinors from L2; ordinary loads when several right-hand-side groups read the same
+// links one after another and must find them in L2.
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_maybe_nt(const char *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+    else return *reinterpret_cast<const T *>(p);
+}
+template <int P, typename R, bool NT>
 __device__ __forceinline__ void ld_link_elem(Cx<R> *o, const char *plane, unsigned off) {
     if constexpr (P == P64) {
-        const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(plane + off));
+        const dvec2 v = ld_maybe_nt<dvec2, NT>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
     } else if constexpr (P == P32) {
-        const fvec4 v = __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(plane + off));
+        const fvec4 v = ld_maybe_nt<fvec4, NT>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
         o[1] = {(R)v.z, (R)v.w};
     } else {
-        const hvec4 v = __builtin_nontemporal_load(reinterpret_cast<const hvec4 *>(plane + off));
+        const hvec4 v = ld_maybe_nt<hvec4, NT>(plane + off);
         o[0] = {(R)(float)v[0], (R)(float)v[1]};
         o[1] = {(R)(float)v[2], (R)(float)v[3]};
     }
@@ -237,18 +253,32 @@ __device__ __forceinline__ void block_reduce_to(double (&v)[NV], double *dst, si
     __syncthreads();
 }
 
+// ---- deterministic wave reduction of NV doubles; result written by lane 0 ----
+template <int NV>
+__device__ __forceinline__ void wave_reduce_to(double (&v)[NV], double *dst, size_t dst_stride) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) dst[(size_t)k * dst_stride] = v[k];
+    }
+}
+
 // Site coordinates of checkerboard index i on output parity par.
 struct SiteXY {
     int xh, b, y, z, t;
 };
 __device__ __forceinline__ SiteXY cb_coords(const Geom &g, int i, int par) {
     SiteXY c;
-    c.xh = i % g.Lxh;
-    int rest = i / g.Lxh;
-    c.y = rest % g.L[1];
-    rest /= g.L[1];
-    c.z = rest % g.L[2];
-    c.t = rest / g.L[2];
+    const int q1 = (int)fdiv((uint32_t)i, g.dLxh);   // i / (Lx/2)
+    c.xh = i - q1 * g.Lxh;
+    const int q2 = (int)fdiv((uint32_t)q1, g.dLy);   // / Ly
+    c.y = q1 - q2 * g.L[1];
+    c.t = (int)fdiv((uint32_t)q2, g.dLz);            // / Lz
+    c.z = q2 - c.t * g.L[2];
     c.b = (c.y + c.z + c.t + par) & 1;  // x = 2*xh + b
     return c;
 }
@@ -259,14 +289,17 @@ __device__ __forceinline__ SiteXY cb_coords(const Geom &g, int i, int par) {
 // still in L2 when the second hop needs it (in memory order the two uses lie 2*Lz planes
 // apart).  Requires zblk | Lz; with Lxh*Ly a multiple of the block size every block stays
 // inside one plane, so loads stay coalesced.
-__device__ __forceinline__ int visit_order(int l, const Geom &g, int zblk) {
-    if (zblk <= 0) return l;
-    const int S = g.Lxh * g.L[1];
-    const int pl = l / S, within = l - pl * S;
-    const int per_zb = zblk * g.L[3];
-    const int zb = pl / per_zb, rem = pl - zb * per_zb;
-    const int t = rem / zblk, zi = rem - t * zblk;
-    return ((zb * zblk + zi) + g.L[2] * t) * S + within;
+struct VisitOrder {
+    int zblk = 0;
+    FastDiv plane, per_zb, zb;  // division by Lxh*Ly, zblk*Lt and zblk
+};
+__device__ __forceinline__ int visit_order(int l, const Geom &g, const VisitOrder &v) {
+    if (v.zblk <= 0) return l;
+    const int S = (int)v.plane.d;
+    const int pl = (int)fdiv((uint32_t)l, v.plane), within = l - pl * S;
+    const int zb = (int)fdiv((uint32_t)pl, v.per_zb), rem = pl - zb * (int)v.per_zb.d;
+    const int t = (int)fdiv((uint32_t)rem, v.zb), zi = rem - t * v.zblk;
+    return ((zb * v.zblk + zi) + g.L[2] * t) * S + within;
 }
 
 // Block index remapped so that each XCD (blocks are dealt round-robin to 8 XCDs)

@@ -1,0 +1,383 @@
+// Parity hop of the Wilson operator (Eq. (1), Sec. 2.1):
+//
+//   out(x) = cH * sum_mu [ (1 - gamma_mu) U_mu(x) in(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag in(x-mu) ]
+//            (+ y(x)) (+ cz * z(x)),   for every site x of the output parity,
+//
+// with optional gamma5 on the input and on the hop result (used for M^dag = g5 M g5),
+// and an optional fused reduction of the result (|out|^2, <w,out>, or <out,y> and |out|^2).
+//
+// One lane owns one output site and `RPT` right-hand sides; every link is loaded once
+// per site and reused for those right-hand sides.  The 4x4 spin structure is applied
+// through spin projection: (1 -/+ gamma_mu) has rank 2, so only a two-spinor "half
+// spinor" h is multiplied by the link (two SU(3) mat-vecs instead of four) and the
+// other two spin rows are rebuilt from it.  In the Dirac basis (gamma_t diagonal)
+// the t projections are (0, 0, 2psi2, 2psi3) forward and (2psi0, 2psi1, 0, 0) backward,
+// so a t-hop reads only two spins of its neighbour.
+//
+// Links are stored either in full (18 reals, antiperiodic sign folded into the t-links of
+// the t = Lt-1 slice) or, for SU(3) fields, as their first two rows (12 reals: a third
+// less link traffic, the largest part of the kernel's bytes); the third row is then
+// rebuilt as conj(row0 x row1) and the boundary sign is applied to the two t-hops that
+// cross t = Lt-1 <-> 0.
+#pragma once
+// Kernel templates; each dslash_<precision>.hip instantiates one precision pair.
+#include <cstdio>
+
+#include "common.h"
+#include "device.h"
+
+namespace wl {
+
+// --- spin projection / reconstruction tables (Dirac basis) ------------------------
+// forward uses (1 - gamma_mu), backward (1 + gamma_mu).  psi: 4 spins x 3 colours.
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void project(const Cx<R> (&p)[4][3], Cx<R> (&h)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 0) {
+            if constexpr (FWD) { h[0][c] = cadd_i(p[0][c], p[3][c]); h[1][c] = cadd_i(p[1][c], p[2][c]); }
+            else               { h[0][c] = csub_i(p[0][c], p[3][c]); h[1][c] = csub_i(p[1][c], p[2][c]); }
+        } else if constexpr (MU == 1) {
+            if constexpr (FWD) { h[0][c] = cadd(p[0][c], p[3][c]); h[1][c] = csub(p[1][c], p[2][c]); }
+            else               { h[0][c] = csub(p[0][c], p[3][c]); h[1][c] = cadd(p[1][c], p[2][c]); }
+        } else if constexpr (MU == 2) {
+            if constexpr (FWD) { h[0][c] = cadd_i(p[0][c], p[2][c]); h[1][c] = csub_i(p[1][c], p[3][c]); }
+            else               { h[0][c] = csub_i(p[0][c], p[2][c]); h[1][c] = cadd_i(p[1][c], p[3][c]); }
+        } else {
+            if constexpr (FWD) { h[0][c] = cadd(p[2][c], p[2][c]); h[1][c] = cadd(p[3][c], p[3][c]); }
+            else               { h[0][c] = cadd(p[0][c], p[0][c]); h[1][c] = cadd(p[1][c], p[1][c]); }
+        }
+    }
+}
+
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void reconstruct(Cx<R> (&acc)[4][3], const Cx<R> (&u)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 3) {
+            if constexpr (FWD) { acc[2][c] = cadd(acc[2][c], u[0][c]); acc[3][c] = cadd(acc[3][c], u[1][c]); }
+            else               { acc[0][c] = cadd(acc[0][c], u[0][c]); acc[1][c] = cadd(acc[1][c], u[1][c]); }
+        } else {
+            acc[0][c] = cadd(acc[0][c], u[0][c]);
+            acc[1][c] = cadd(acc[1][c], u[1][c]);
+            if constexpr (MU == 0) {
+                if constexpr (FWD) { acc[2][c] = csub_i(acc[2][c], u[1][c]); acc[3][c] = csub_i(acc[3][c], u[0][c]); }
+                else               { acc[2][c] = cadd_i(acc[2][c], u[1][c]); acc[3][c] = cadd_i(acc[3][c], u[0][c]); }
+            } else if constexpr (MU == 1) {
+                if constexpr (FWD) { acc[2][c] = csub(acc[2][c], u[1][c]); acc[3][c] = cadd(acc[3][c], u[0][c]); }
+                else               { acc[2][c] = cadd(acc[2][c], u[1][c]); acc[3][c] = csub(acc[3][c], u[0][c]); }
+            } else {
+                if constexpr (FWD) { acc[2][c] = csub_i(acc[2][c], u[0][c]); acc[3][c] = cadd_i(acc[3][c], u[1][c]); }
+                else               { acc[2][c] = cadd_i(acc[2][c], u[0][c]); acc[3][c] = csub_i(acc[3][c], u[1][c]); }
+            }
+        }
+    }
+}
+
+// Spins of the neighbour a direction needs: t forward reads 2,3; t backward 0,1.
+template <int MU, bool FWD>
+__device__ __forceinline__ constexpr bool spin_needed(int s) {
+    return MU != 3 ? true : (FWD ? s >= 2 : s < 2);
+}
+
+// NE: stored complex entries per link (9, or 6 = the first two rows of an SU(3) matrix).
+// sgn: boundary sign of this hop (only used with NE == 6; full links carry it folded in).
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD>
+__device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
+                                        int r0, int nbr, int link_par, int link_site, real_t<SP> sgn, int stride) {
+    using R = real_t<SP>;
+    // link U_mu(x) (forward, at the output site) or U_mu(x - mu) (backward, at the neighbour)
+    Cx<R> U[3][3];
+    {
+        constexpr int NL = LinkElems<GP, NE>::N, CPL = LinkPack<GP>::CPL;
+        Cx<R> ue[NL * CPL];
+        const unsigned loff = (unsigned)link_site * LinkPack<GP>::EB;
+#pragma unroll
+        for (int e = 0; e < NL; e++)
+            ld_link_elem<GP, R, LNT>(&ue[e * CPL], lplane<GP>(a.gauge, (link_par * 4 + MU) * NL + e, stride), loff);
+#pragma unroll
+        for (int e = 0; e < NE; e++) U[e / 3][e % 3] = ue[e];
+    }
+    if constexpr (NE == 6) {
+        // third row of an SU(3) matrix: complex conjugate of (row 0) x (row 1)
+        const Cx<R> c0 = csub(cmul(U[0][1], U[1][2]), cmul(U[0][2], U[1][1]));
+        const Cx<R> c1 = csub(cmul(U[0][2], U[1][0]), cmul(U[0][0], U[1][2]));
+        const Cx<R> c2 = csub(cmul(U[0][0], U[1][1]), cmul(U[0][1], U[1][0]));
+        U[2][0] = {c0.re, -c0.im};
+        U[2][1] = {c1.re, -c1.im};
+        U[2][2] = {c2.re, -c2.im};
+    }
+
+    constexpr int CPE = SpinorPack<SP>::CPE, NEL = SpinorPack<SP>::NEL;
+    // the t-hops read one spin half of the neighbour (components 6h..6h+5): the upper half
+    // forward, the lower half backward, swapped when gamma5 acts on the input
+    constexpr int half = MU == 3 ? ((FWD ? 1 : 0) ^ (G5 ? 1 : 0)) : -1;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        // with one RHS per lane the kernel has already returned when it is inactive
+        if (RPT > 1 && !act[r]) continue;
+        const unsigned soff = (unsigned)nbr * 16u;
+        Cx<R> comp[12];
+#pragma unroll
+        for (int e = 0; e < NEL; e++) {
+            const bool need = half < 0 || ((e + 1) * CPE > 6 * half && e * CPE < 6 * half + 6);
+            if (need) ld_elem<SP, R>(&comp[e * CPE], splane(a.in.data, (r0 + r) * NEL + e, stride), soff);
+            else
+#pragma unroll
+                for (int k = 0; k < CPE; k++) comp[e * CPE + k] = {R(0), R(0)};
+        }
+        Cx<R> p[4][3];
+        // gamma5 on the input: (g5 psi)_s = -psi_{s^2} (a compile-time choice: the values
+        // of both permutations would otherwise have to stay live across a branch)
+        if constexpr (G5) {
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    p[sp][c] = spin_needed<MU, FWD>(sp)
+                                   ? Cx<R>{-comp[(sp ^ 2) * 3 + c].re, -comp[(sp ^ 2) * 3 + c].im}
+                                   : Cx<R>{R(0), R(0)};
+        } else {
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    p[sp][c] = spin_needed<MU, FWD>(sp) ? comp[sp * 3 + c] : Cx<R>{R(0), R(0)};
+        }
+        Cx<R> h[2][3];
+        project<MU, FWD, R>(p, h);
+        if constexpr (SP == P16) {
+            const R sc = (R)a.in.scale[(size_t)(r0 + r) * stride + nbr];
+#pragma unroll
+            for (int k = 0; k < 2; k++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) h[k][c] = cscale(h[k][c], sc);
+        }
+        Cx<R> u[2][3];
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int a_ = 0; a_ < 3; a_++) {
+                Cx<R> t = {R(0), R(0)};
+#pragma unroll
+                for (int b_ = 0; b_ < 3; b_++) {
+                    if constexpr (FWD) t = cfma(t, U[a_][b_], h[k][b_]);       // U h
+                    else               t = cfma_conj(t, U[b_][a_], h[k][b_]);  // U^dag h
+                }
+                u[k][a_] = NE == 6 && MU == 3 ? cscale(t, sgn) : t;
+            }
+        reconstruct<MU, FWD, R>(acc[r], u);
+    }
+    // keep the next direction's gathers from being hoisted above this one: with all eight
+    // directions in flight at once the kernel needs more registers than it can keep
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// One output site i (all RPT right-hand sides of this lane): gather, project, multiply,
+// reconstruct, epilogue, store; the site's reduction terms are added to red[r][*].
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT>
+__device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, int r0, const bool (&act)[RPT],
+                                         double (&red)[RPT][3]) {
+    using R = real_t<SP>;
+    const Geom &g = a.g;
+    const int stride = g.stride;
+    const int par = a.par, opar = 1 - par;
+    const SiteXY c = cb_coords(g, i, par);
+    const int row = i - c.xh;
+    const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
+    const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
+    const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
+    const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
+    const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
+    const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
+    const int tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
+    const int tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+
+    Cx<R> acc[RPT][4][3];
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc[r][s][k] = {R(0), R(0)};
+
+    const R one = R(1);
+    const R sgn_tf = (NE == 6 && c.t == g.L[3] - 1) ? -one : one;  // forward hop across t = Lt-1 -> 0
+    const R sgn_tb = (NE == 6 && c.t == 0) ? -one : one;            // backward hop across t = 0 -> Lt-1
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true>(acc, a, act, r0, xp, par, i, one, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false>(acc, a, act, r0, xm, opar, xm, one, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true>(acc, a, act, r0, yp, par, i, one, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false>(acc, a, act, r0, ym, opar, ym, one, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true>(acc, a, act, r0, zp, par, i, one, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false>(acc, a, act, r0, zm, opar, zm, one, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true>(acc, a, act, r0, tp, par, i, sgn_tf, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride);
+
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        if (RPT > 1 && !act[r]) continue;
+        const int rhs = r0 + r;
+        const R cH = (R)a.cH[rhs];
+        Cx<R> o[12];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // gamma5 on the hop result: (g5 v)_s = -v_{s^2}
+                Cx<R> v = a.g5out ? Cx<R>{-acc[r][s ^ 2][k].re, -acc[r][s ^ 2][k].im} : acc[r][s][k];
+                o[s * 3 + k] = cscale(v, cH);
+            }
+        Cx<R> yv[12];
+        if (a.has_y) {
+            load_site<SP, R>(yv, a.y, stride, rhs, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], yv[k]);
+        }
+        if (a.has_z) {
+            Cx<R> zv[12];
+            load_site<SP, R>(zv, a.z, stride, rhs, i);
+            const R cz = (R)a.cz;
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
+        }
+        if (valid && !a.nostore) store_site<SP, R>(a.out, stride, rhs, i, o);
+        if (!valid || a.red == RED_NONE) continue;
+        if (a.red == RED_NORM2) {
+            for (int k = 0; k < 12; k++) red[r][0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        } else if (a.red == RED_DOT) {
+            Cx<R> wv[12];
+            load_site<SP, R>(wv, a.w, stride, rhs, i);
+            for (int k = 0; k < 12; k++) {  // <w, o> = sum conj(w) o
+                red[r][0] += (double)wv[k].re * o[k].re + (double)wv[k].im * o[k].im;
+                red[r][1] += (double)wv[k].re * o[k].im - (double)wv[k].im * o[k].re;
+            }
+        } else {
+            for (int k = 0; k < 12; k++) {  // <o, y> and |o|^2
+                red[r][0] += (double)o[k].re * yv[k].re + (double)o[k].im * yv[k].im;
+                red[r][1] += (double)o[k].re * yv[k].im - (double)o[k].im * yv[k].re;
+                red[r][2] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+            }
+        }
+    }
+}
+
+// Block b (in XCD-contiguous order when xcd_remap) covers site tile b / ngroups and
+// right-hand-side group b % ngroups: the groups that share a tile's links run next to
+// each other on one XCD, so the links come from HBM once and from L2 after that.
+// A tile is `blockDim` consecutive checkerboard indices, optionally permuted plane-wise
+// (zblk); one lane processes one site.
+// With wsplit, a tile is 64 sites and the waves of a block take successive RHS groups of
+// it: the block's waves read the same links at the same time on one CU, so a link is
+// requested from L2 once per block instead of once per group.  Each wave then reduces
+// its own partial sums (no block barrier).
+// Register budget: waves per SIMD the compiler must fit (FP64: 2, else 4 up to two RHS
+// per lane, 3 beyond); without it the scheduler hoists the gathers of all eight
+// directions and the single-RHS kernels spill.
+template <int SP, int RPT>
+struct HopOcc {
+    static constexpr int value = SP == P64 ? 2 : (RPT <= 2 ? 4 : 3);
+};
+
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<SP, RPT>::value)))
+hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
+    const Geom &g = a.g;
+    const int ngroups = a.nrhs / RPT;
+    const int lb = xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int nw = (int)blockDim.x >> 6;
+    const int bpt = wsplit ? ngroups / nw : ngroups;  // blocks per tile
+    const int tile = lb / bpt;
+    int r0, l;
+    if (wsplit) {
+        r0 = __builtin_amdgcn_readfirstlane(((lb - tile * bpt) * nw + ((int)threadIdx.x >> 6)) * RPT);
+        l = tile * 64 + ((int)threadIdx.x & 63);
+    } else {
+        r0 = (lb - tile * bpt) * RPT;
+        l = tile * (int)blockDim.x + (int)threadIdx.x;
+    }
+    bool act[RPT];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        act[r] = (r0 + r < a.nrhs) && (a.state == nullptr || (a.state[r0 + r].phase & a.run_mask));
+        any |= act[r];
+    }
+    if (!any) return;  // uniform over the block (over the wave with wsplit)
+
+    double red[RPT][3];
+#pragma unroll
+    for (int r = 0; r < RPT; r++) red[r][0] = red[r][1] = red[r][2] = 0.0;
+
+    const bool valid = l < g.Vh;
+    const int i = valid ? visit_order(l, g, vo) : g.Vh - 1;
+    hop_site<SP, GP, RPT, NE, G5, LNT>(a, i, valid, r0, act, red);
+
+    const int nv = red_nvals(a.red);
+    if (nv == 0) return;
+    const int ntiles = (int)gridDim.x / bpt;
+    const int ps = a.pstride ? a.pstride : ntiles;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        if (!act[r]) continue;
+        double *dst = a.partials + (size_t)(r0 + r) * nv * ps + tile;
+        if (nv == 1) {
+            double v[1] = {red[r][0]};
+            if (wsplit) wave_reduce_to<1>(v, dst, ps);
+            else block_reduce_to<1>(v, dst, ps);
+        } else if (nv == 2) {
+            double v[2] = {red[r][0], red[r][1]};
+            if (wsplit) wave_reduce_to<2>(v, dst, ps);
+            else block_reduce_to<2>(v, dst, ps);
+        } else {
+            double v[3] = {red[r][0], red[r][1], red[r][2]};
+            if (wsplit) wave_reduce_to<3>(v, dst, ps);
+            else block_reduce_to<3>(v, dst, ps);
+        }
+    }
+}
+
+template <int SP, int GP, int NE, bool G5, bool LNT>
+static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    const int ngroups = a.nrhs / c.rpt;
+    dim3 grid(hop_nblocks(a, c) * (c.wsplit ? ngroups / (c.block / 64) : ngroups));
+    dim3 block(c.block);
+    const int remap = c.xcd;
+    // Unused dynamic LDS caps the blocks resident per CU (160 KB of LDS per CU), so fewer
+    // sites are in flight per XCD and their neighbour data stays in L2.
+    const size_t lds = (size_t)c.lds_kb * 1024;
+    VisitOrder vo;
+    if (c.zblk > 0) {
+        vo.zblk = c.zblk;
+        vo.plane = make_fastdiv((uint32_t)(a.g.Lxh * a.g.L[1]));
+        vo.per_zb = make_fastdiv((uint32_t)(c.zblk * a.g.L[3]));
+        vo.zb = make_fastdiv((uint32_t)c.zblk);
+    }
+    switch (c.rpt) {
+        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
+        case 3:
+            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 3, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            break;
+        case 4:
+            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 4, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Links are loaded non-temporally when one group covers every right-hand side (each link
+// is read once per launch) and through L2 otherwise.
+template <int SP, int GP, int NE, bool G5>
+static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    if (a.nrhs == c.rpt) return launch_hop_k<SP, GP, NE, G5, true>(a, c, s);
+    return launch_hop_k<SP, GP, NE, G5, false>(a, c, s);
+}
+
+template <int SP, int GP>
+hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    if (a.g5in) return a.recon == 12 ? launch_hop_t<SP, GP, 6, true>(a, c, s) : launch_hop_t<SP, GP, 9, true>(a, c, s);
+    return a.recon == 12 ? launch_hop_t<SP, GP, 6, false>(a, c, s) : launch_hop_t<SP, GP, 9, false>(a, c, s);
+}
+
+}  // namespace wl

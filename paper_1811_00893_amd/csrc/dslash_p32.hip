@@ -1,0 +1,6 @@
+// Parity hop kernels for FP32 spinors, FP32 links.
+#include "dslash_kernels.h"
+
+namespace wl {
+template hipError_t launch_hop_r<P32, P32>(const HopArgs &, const LaunchCfg &, hipStream_t);
+}  // namespace wl

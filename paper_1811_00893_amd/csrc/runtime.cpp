@@ -33,6 +33,13 @@ Geom make_geom(const int32_t dims[4]) {
     g.sy = g.Lxh;
     g.sz = g.Lxh * dims[1];
     g.st = g.Lxh * dims[1] * dims[2];
+    g.dLxh = make_fastdiv((uint32_t)g.Lxh);
+    g.dLy = make_fastdiv((uint32_t)dims[1]);
+    g.dLz = make_fastdiv((uint32_t)dims[2]);
+    // the multiply-high division is exact for every n < 2^31; spot-check the sizes in use
+    for (const FastDiv *f : {&g.dLxh, &g.dLy, &g.dLz})
+        for (uint32_t n : {0u, 1u, f->d - 1, f->d, (uint32_t)g.Vh - 1, (uint32_t)g.Vh, 0x7fffffffu})
+            if (fdiv(n, *f) != n / f->d) throw Error(WILSON_INVALID_ARG, "index division self-check failed");
     return g;
 }
 
@@ -137,8 +144,8 @@ void wilson_ctx::load_tune_cache() {
     if (env && std::strcmp(env, "0") == 0) tune_enabled = false;
     const char *fc = std::getenv("WILSON_HOP_CFG");
     if (fc) {
-        forced = std::sscanf(fc, "%d,%d,%d,%d,%d", &forced_cfg.block, &forced_cfg.rpt, &forced_cfg.xcd,
-                             &forced_cfg.zblk, &forced_cfg.lds_kb) >= 4;
+        forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d", &forced_cfg.block, &forced_cfg.rpt, &forced_cfg.xcd,
+                             &forced_cfg.zblk, &forced_cfg.lds_kb, &forced_cfg.wsplit) >= 4;
     }
     const char *path = std::getenv("WILSON_TUNE_CACHE");
     if (!path || !*path) return;
@@ -153,8 +160,9 @@ void wilson_ctx::load_tune_cache() {
         if (k1 == std::string::npos) continue;
         const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
         LaunchCfg c;
-        if (std::sscanf(line.c_str() + k1, "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d",
-                        &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb) == 5)
+        if (std::sscanf(line.c_str() + k1,
+                        "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d",
+                        &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit) >= 5)
             tuned[key] = c;
     }
 }
@@ -163,7 +171,8 @@ void wilson_ctx::save_tune_entry(const std::string &key, const LaunchCfg &c, dou
     if (tune_path.empty()) return;
     std::ofstream out(tune_path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
-        << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"ms\": " << ms << "}\n";
+        << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"wsplit\": " << c.wsplit
+        << ", \"ms\": " << ms << "}\n";
 }
 
 namespace wl {
@@ -189,20 +198,23 @@ static LaunchCfg default_cfg(const HopArgs &a) {
 // its inputs, so repeated launches are harmless) and keep the fastest.
 static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
     std::vector<LaunchCfg> cands;
-    for (int block : {64, 128, 256})
-        for (int rpt : {1, 2, 3, 4})
-            for (int xcd : {0, 1})
-                for (int zblk : {0, 4, 8})
-                    for (int lds_kb : {0, 24, 40, 56}) {
-                        if (xcd == 0 && (zblk != 0 || lds_kb != 0)) continue;
-                        LaunchCfg c;
-                        c.block = block;
-                        c.rpt = rpt;
-                        c.xcd = xcd;
-                        c.zblk = zblk;
-                        c.lds_kb = lds_kb;
-                        if (hop_cfg_valid(a, c)) cands.push_back(c);
-                    }
+    for (int wsplit : {0, 1})
+        for (int block : {64, 128, 192, 256})
+            for (int rpt : {1, 2, 3, 4})
+                for (int xcd : {0, 1})
+                    for (int zblk : {0, 4, 8})
+                        for (int lds_kb : {0, 24, 40, 56}) {
+                            if (xcd == 0 && (zblk != 0 || lds_kb != 0)) continue;
+                            if (wsplit && a.nrhs == 1) continue;
+                            LaunchCfg c;
+                            c.block = block;
+                            c.rpt = rpt;
+                            c.xcd = xcd;
+                            c.zblk = zblk;
+                            c.lds_kb = lds_kb;
+                            c.wsplit = wsplit;
+                            if (hop_cfg_valid(a, c)) cands.push_back(c);
+                        }
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
@@ -222,8 +234,8 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         WL_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
         if (std::getenv("WILSON_TUNE_VERBOSE"))
-            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d: %.2f us\n", hop_key(a).c_str(),
-                         c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, per * 1e3);
+            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d: %.2f us\n", hop_key(a).c_str(),
+                         c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, c.wsplit, per * 1e3);
         if (per < bms) {
             bms = per;
             best = c;
@@ -248,6 +260,8 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
         if (!hop_cfg_valid(a, cfg)) {  // keep the pinned order and block, fit the RHS split
             cfg.rpt = default_cfg(a).rpt;
             if (cfg.zblk > 0 && a.g.L[2] % cfg.zblk) cfg.zblk = 0;
+            if (!hop_cfg_valid(a, cfg)) cfg.wsplit = 0;
+            if (!hop_cfg_valid(a, cfg)) cfg.block = 256;
         }
     } else if (it != ctx->tuned.end() && hop_cfg_valid(a, it->second)) {
         cfg = it->second;

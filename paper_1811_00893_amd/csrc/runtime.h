@@ -113,7 +113,7 @@ struct wilson_ctx {
     // ---- autotuner ----
     std::map<std::string, wl::LaunchCfg> tuned;
     bool tune_enabled = true;
-    bool forced = false;   // WILSON_HOP_CFG="block,rpt,xcd,zblk[,lds_kb]" pins every hop launch (tests)
+    bool forced = false;   // WILSON_HOP_CFG="block,rpt,xcd,zblk[,lds_kb[,wsplit]]" pins every hop launch (tests)
     wl::LaunchCfg forced_cfg;
     bool tune_loaded = false;
     std::string tune_path;

@@ -219,6 +219,40 @@ def test_batched_point_sources(L, ctx):
     L.wilson_gauge_free(ctx, g)
 
 
+@pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1"])
+def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
+    """The batched solve with the hop's RHS groups split over the waves of a block (each
+    wave writes its own partial sums of the fused reductions) converges for every RHS
+    to the oracle's residual test and agrees with the default configuration."""
+    dims = (4, 4, 8, 8)  # Vh = 512: eight 64-site tiles
+    k, tol = 0.125, 1e-10
+    U = inputs.gauge_field(dims, eps=0.3, seed=1005)
+    b = inputs.point_sources(dims)
+    ref = {}
+    for forced in (False, True):
+        if forced:
+            monkeypatch.setenv("WILSON_HOP_CFG", cfg)
+        c = L.wilson_context_create()
+        g = L.wilson_gauge_load(c, U.to(DEV), dims, L.WILSON_GAUGE_FP32)
+        try:
+            for prec in (0, 1):
+                x = torch.zeros_like(b, device=DEV)
+                st, _ = L.wilson_solve_ex(c, g, x, b.to(DEV), 12, [k] * 12, [tol] * 12, {"precision": prec})
+                assert st == 0, (cfg, prec, st, L.wilson_last_error())
+                xs = x.cpu().numpy()
+                if not forced:
+                    ref[prec] = xs
+                    continue
+                for j in range(12):
+                    assert oracle_residual(xs[j], b[j].numpy(), U.numpy(), k, dims) < tol, (cfg, prec, j)
+                d = rel(xs, ref[prec])
+                print(f"{cfg} prec {prec}: wave-split vs default {d:.2e}")
+                assert d < 1e-8
+        finally:
+            L.wilson_gauge_free(c, g)
+            L.wilson_context_destroy(c)
+
+
 def test_solve_edge_cases(L, ctx):
     dims = (4, 4, 2, 4)
     U, b = setup_case(dims, 8)
@@ -275,11 +309,13 @@ def test_full_size_sampled_dslash(L, ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2"])
+@pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2",
+                                 "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
-    XCD tile order, plane-blocked visiting order) gives the oracle's result; the lattice
-    has a ragged last block for every block size."""
+    XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
+    waves of a block) gives the oracle's result; the lattice has a ragged last block for
+    every block size."""
     monkeypatch.setenv("WILSON_HOP_CFG", cfg)
     dims = (6, 4, 8, 10)  # Vh = 960: not a multiple of 64, 128 or 256
     U, _ = setup_case(dims, 9)
