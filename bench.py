@@ -34,9 +34,12 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--dslash-only", action="store_true", help="only the Dslash section and the copy probe")
-    p.add_argument("--requests", type=int, default=40, help="serving: number of requests")
-    p.add_argument("--load", type=float, default=0.8, help="serving: offered load / FIFO capacity")
-    p.add_argument("--step-iters", type=int, default=8, help="serving: iterations per scheduler turn")
+    p.add_argument("--requests", type=int, default=60, help="serving: requests per phase")
+    p.add_argument("--loads", type=lambda v: [float(x) for x in v.split(",")], default=[0.5, 0.8, 1.0],
+                   help="serving: offered loads as fractions of the server's closed-loop capacity")
+    p.add_argument("--outstanding", type=int, default=24, help="serving: requests in flight in the capacity run")
+    p.add_argument("--step-iters", type=int, default=32, help="serving: most iterations per scheduler turn")
+    p.add_argument("--turn-ms", type=float, default=3.0, help="serving: target duration of a scheduler turn")
     p.add_argument("--hbm-budget", type=float, default=200e9, help="serving: device bytes for fields + batches")
     return p.parse_args()
 
@@ -91,11 +94,19 @@ def run_serving(args):
     """Serving: a Poisson stream of solve requests over four lattice sizes, each request on
     one of two seeded gauge fields per size (eps ~ U[0.2, 0.4]), kappa ~ U[0.115, 0.125],
     tol in {1e-8, 1e-10, 1e-12}, 1-12 Gaussian right-hand sides; mixed precision (FP32 inner,
-    FP64 outer).  The same trace is first served one request at a time (FIFO, the plain
-    path) to measure its capacity; arrivals are then generated at `--load` x that capacity
-    and replayed through the continuous-batching server.  Latency = arrival -> solution in
-    device memory.  FIFO latencies on the same arrivals follow from its measured service
-    times (one request at a time)."""
+    FP64 outer).  Sources are generated when a request arrives and released when it
+    completes, so any number of requests fits in memory.
+
+      1. FIFO baselines, every request of the trace served alone, one after the other:
+         (a) all its right-hand sides in one mixed-precision batched solve; (b) the plain
+         path: each right-hand side by the FP64 solver alone.  Their service times give
+         FIFO latencies on any arrival sequence.
+      2. Capacity: the continuous-batching server fed as fast as it drains (at most
+         `--outstanding` requests waiting or running): RHS/s and requests/s.
+      3. For each offered load in `--loads` (fractions of that capacity): Poisson arrivals
+         at load x capacity replayed through the server; p50/p99 latency (arrival ->
+         solution in device memory) and throughput, next to FIFO on the same arrivals.
+    """
     import numpy as np
     import torch
 
@@ -118,83 +129,230 @@ def run_serving(args):
         trace.append(dict(gid=(si, k), kappa=float(rng.uniform(0.115, 0.125)),
                           tol=float([1e-8, 1e-10, 1e-12][int(rng.integers(0, 3))]),
                           nrhs=int(rng.integers(1, 13)), seed=4000 + i))
+    rhs_total = sum(t["nrhs"] for t in trace)
     U = {gid: inputs.gauge_field(d, eps=e, seed=s, device=dev) for gid, (d, e, s) in pool.items()}
-    B = [inputs.gaussian_source(pool[t["gid"]][0], seed=t["seed"], nrhs=t["nrhs"], device=dev) for t in trace]
+
+    def source(i):
+        t = trace[i]
+        return inputs.gaussian_source(pool[t["gid"]][0], seed=t["seed"], nrhs=t["nrhs"], device=dev)
+
+    def progress(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
     opts = {"precision": 1, "maxiter": 100000}
 
-    # FIFO: one request at a time through wilson_solve_ex (all its RHS together)
+    # 1. FIFO: one request at a time through wilson_solve_ex (all its RHS together)
     ctx = L.wilson_context_create()
     G = {gid: L.wilson_gauge_load(ctx, U[gid], pool[gid][0], L.WILSON_GAUGE_FP32) for gid in pool}
-    def fifo_once(i):
+
+    def fifo_once(i, b):
         t = trace[i]
-        x = torch.zeros_like(B[i])
-        st, info = L.wilson_solve_ex(ctx, G[t["gid"]], x, B[i], t["nrhs"], t["kappa"], t["tol"], opts)
+        x = torch.zeros_like(b)
+        st, _ = L.wilson_solve_ex(ctx, G[t["gid"]], x, b, t["nrhs"], t["kappa"], t["tol"], opts)
         L.check(st, "fifo solve")
-    for i in range(min(4, nreq)):  # warm the tuner
-        fifo_once(i)
+
+    # warm the tuner: every lattice size and class of RHS count before anything is timed
+    for si, d in enumerate(sizes):
+        for n in (1, 2, 4, 8, 12):
+            b = inputs.gaussian_source(d, seed=3900 + n, nrhs=n, device=dev)
+            x = torch.zeros_like(b)
+            L.check(L.wilson_solve_ex(ctx, G[(si, 0)], x, b, n, 0.12, 1e-8, opts)[0], "warm-up solve")
+            del b, x
+    progress("tuner warm")
     service = []
     torch.cuda.synchronize()
     for i in range(nreq):
+        b = source(i)
+        torch.cuda.synchronize()
         s0 = time.perf_counter()
-        fifo_once(i)
+        fifo_once(i, b)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - s0)
+        del b
+        if (i + 1) % 50 == 0:
+            progress(f"fifo {i + 1}/{nreq}")
+    fifo_total = sum(service)
+
+    # the plain path: one request at a time, each right-hand side by the FP64 solver alone
+    popts = {"precision": 0, "maxiter": 100000}
+    plain = []
+    for i in range(nreq):
+        t = trace[i]
+        b = source(i)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for j in range(t["nrhs"]):
+            x = torch.zeros_like(b[j])
+            st, _ = L.wilson_solve_ex(ctx, G[t["gid"]], x, b[j], 1, t["kappa"], t["tol"], popts)
+            L.check(st, "plain FP64 solve")
+        torch.cuda.synchronize()
+        plain.append(time.perf_counter() - s0)
+        del b
+        if (i + 1) % 50 == 0:
+            progress(f"plain fp64 {i + 1}/{nreq}")
+    plain_total = sum(plain)
     for g in G.values():
         L.wilson_gauge_free(ctx, g)
     L.wilson_context_destroy(ctx)
-    fifo_total = sum(service)
-    cap = nreq / fifo_total
-    lam = args.load * cap
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
-    # FIFO latencies on these arrivals
-    t_free, fifo_lat = 0.0, []
-    for a, sv in zip(arrivals, service):
-        start = max(a, t_free)
-        t_free = start + sv
-        fifo_lat.append(t_free - a)
 
-    # continuous batching
-    sch, eng = make_server(hbm_budget=args.hbm_budget, nslots=12, step_iters=args.step_iters, precision=1)
+    # the continuous-batching server
+    sch, eng = make_server(hbm_budget=args.hbm_budget, nslots=12, step_iters=args.step_iters, precision=1,
+                           turn_ms=args.turn_ms)
     for gid, (d, e, s) in pool.items():
         sch.register_gauge(gid, d, eng.load_gauge(gid, U[gid], d))
-    warm = Request(rid=-1, gauge_id=(0, 0), kappa=0.12, tol=1e-10, b=B[0][:1].contiguous())
-    sch.submit(warm)
+    eng.alloc_solution = lambda req: torch.zeros_like(req.b)
+    for si, d in enumerate(sizes):  # one request per lattice size through the server
+        sch.submit(Request(rid=-1 - si, gauge_id=(si, 0), kappa=0.12, tol=1e-8,
+                           b=inputs.gaussian_source(d, seed=3950, nrhs=1, device=dev)))
     sch.run_until_idle()
     sch.completed.clear()
-    reqs = [Request(rid=i, gauge_id=t["gid"], kappa=t["kappa"], tol=t["tol"], b=B[i], maxiter=100000)
-            for i, t in enumerate(trace)]
-    eng.alloc_solution = lambda req: torch.zeros_like(req.b)
-    t0 = time.perf_counter()
-    sch.clock = lambda: time.perf_counter() - t0
-    nxt = 0
-    while nxt < nreq or sch.busy():
-        now = sch.clock()
-        while nxt < nreq and arrivals[nxt] <= now:
-            reqs[nxt].arrival = float(arrivals[nxt])
-            sch.submit(reqs[nxt])
-            nxt += 1
-        if sch.busy():
-            sch.admit()
-            sch.step()
-        elif nxt < nreq:
-            time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
-    wall = sch.clock()
+
+    def serve(arrivals, outstanding=None):
+        """Replay the trace; arrivals None = closed loop with at most `outstanding` requests
+        in the server.  Returns (wall seconds, latencies, failed request ids)."""
+        t0 = time.perf_counter()
+        sch.clock = lambda: time.perf_counter() - t0
+        sch.completed.clear()
+        lat, bad, done, nxt, inflight = [], [], 0, 0, 0
+        while done < nreq:
+            now = sch.clock()
+            while nxt < nreq and ((arrivals is None and inflight < outstanding) or
+                                  (arrivals is not None and arrivals[nxt] <= now)):
+                t = trace[nxt]
+                r = Request(rid=nxt, gauge_id=t["gid"], kappa=t["kappa"], tol=t["tol"], b=source(nxt),
+                            maxiter=100000, arrival=float(arrivals[nxt]) if arrivals is not None else now)
+                if not sch.submit(r):
+                    raise RuntimeError(f"request {nxt} rejected")
+                nxt += 1
+                inflight += 1
+            if sch.busy():
+                sch.admit()
+                sch.step()
+            elif arrivals is not None and nxt < nreq:
+                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
+            for r in sch.completed:  # record and release finished requests
+                lat.append(r.latency)
+                if any(st != 0 for st in r.status):
+                    bad.append(r.rid)
+                r.b = r.x = None
+                done += 1
+                inflight -= 1
+                if done % 100 == 0:
+                    progress(f"served {done}/{nreq}")
+            sch.completed.clear()
+        return sch.clock(), lat, bad
+
+    # 2. capacity of the server (closed loop)
+    wall_c, lat_c, bad_c = serve(None, outstanding=args.outstanding)
+    cap_req = nreq / wall_c
+    progress(f"capacity {rhs_total / wall_c:.1f} RHS/s")
+
+    # 3. open-loop load points
+    points = []
+    for load in args.loads:
+        lam = load * cap_req
+        arrivals = np.cumsum(np.random.default_rng(3500 + int(100 * load)).exponential(1.0 / lam, size=nreq))
+        wall, lat, bad = serve(arrivals)
+        def fifo(times):
+            t_free, out = 0.0, []
+            for a, sv in zip(arrivals, times):
+                t_free = max(a, t_free) + sv
+                out.append(t_free - a)
+            return out, rhs_total / t_free
+        fifo_lat, fifo_rate = fifo(service)
+        plain_lat, plain_rate = fifo(plain)
+        points.append({
+            "offered_load": load, "arrival_rate_per_s": lam,
+            "rhs_per_s": rhs_total / wall, "requests_per_s": nreq / wall,
+            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "fifo_batched_mixed": {"p50_ms": 1e3 * percentile(fifo_lat, 50), "p99_ms": 1e3 * percentile(fifo_lat, 99),
+                                   "rhs_per_s": fifo_rate},
+            "fifo_plain_fp64": {"p50_ms": 1e3 * percentile(plain_lat, 50), "p99_ms": 1e3 * percentile(plain_lat, 99),
+                                "rhs_per_s": plain_rate},
+            "failed_requests": bad,
+        })
+        progress(f"load {load}: p50 {points[-1]['p50_ms']:.0f} ms p99 {points[-1]['p99_ms']:.0f} ms")
     sch.close()
     eng.close()
-    lat = [r.latency for r in sch.completed]
-    bad = [r.rid for r in sch.completed if any(st != 0 for st in r.status)]
-    rhs = sum(t["nrhs"] for t in trace)
     return {
         "metric": METRIC, "workload": "serving", "unit": "solves/s",
-        "value": rhs / wall,
-        "requests": nreq, "rhs": rhs, "offered_load": args.load, "arrival_rate_per_s": lam,
-        "served_p50_ms": 1e3 * percentile(lat, 50), "served_p99_ms": 1e3 * percentile(lat, 99),
-        "requests_per_s": nreq / wall,
-        "fifo_capacity_rhs_per_s": rhs / fifo_total,
-        "fifo_p50_ms": 1e3 * percentile(fifo_lat, 50), "fifo_p99_ms": 1e3 * percentile(fifo_lat, 99),
-        "failed_requests": bad, "rejected": len(sch.rejected),
-        "config": {"lattices": sizes, "gauge_fields_per_size": 2, "nslots": 12, "step_iters": args.step_iters,
-                   "precision": "mixed_fp32", "latency": "arrival to solution in device memory"},
+        "value": rhs_total / wall_c,
+        "requests": nreq, "rhs": rhs_total,
+        "capacity": {"rhs_per_s": rhs_total / wall_c, "requests_per_s": cap_req,
+                     "p50_ms": 1e3 * percentile(lat_c, 50), "p99_ms": 1e3 * percentile(lat_c, 99),
+                     "outstanding": args.outstanding, "failed_requests": bad_c},
+        "fifo_batched_mixed_capacity_rhs_per_s": rhs_total / fifo_total,
+        "fifo_plain_fp64_capacity_rhs_per_s": rhs_total / plain_total,
+        "gain_over_plain_fp64": (rhs_total / wall_c) / (rhs_total / plain_total),
+        "load_points": points,
+        "rejected": len(sch.rejected),
+        "config": {"lattices": sizes, "gauge_fields_per_size": 2, "nslots": 12, "step_iters_max": args.step_iters,
+                   "turn_ms": args.turn_ms,
+                   "precision": "mixed_fp32", "latency": "arrival to solution in device memory",
+                   "loads_relative_to": "closed-loop capacity of the continuous-batching server"},
+    }
+
+
+def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu):
+    """The FP64 oracle timed on the host: an even-odd BiCGStab solve (run for 1 and 1+k
+    iterations, whose difference isolates the cost of an iteration, scaled to the number
+    of iterations the GPU solve took), and the operator units (parity hop, full D) with
+    all threads and the parity hop on one thread."""
+    import numpy as np
+
+    import oracle
+    from paper_1811_00893_amd import counts
+    Un = U.cpu().numpy()
+    bn = (b[0] if nrhs > 1 else b).cpu().numpy()
+    t1 = time.perf_counter()
+    oracle.solve(bn, Un, kappa, dims, 0.0, 1, "bicgstab_eo")
+    one = time.perf_counter() - t1
+    k_it = max(2, min(40, int(args.cpu_seconds / max(one, 1e-3))))
+    t1 = time.perf_counter()
+    oracle.solve(bn, Un, kappa, dims, 0.0, 1 + k_it, "bicgstab_eo")
+    more = time.perf_counter() - t1
+    per_iter = max(more - one, 1e-9) / k_it
+    setup = max(one - per_iter, 0.0)
+    V = int(np.prod(dims))
+
+    def best_of(fn, n=3):
+        ts = []
+        for _ in range(n):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return min(ts)
+
+    hop_s = best_of(lambda: oracle.dslash(bn, Un, kappa, dims, 0))
+    d_s = best_of(lambda: oracle.apply_D(bn, Un, kappa, dims))
+    nthr = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        hop1_s = best_of(lambda: oracle.dslash(bn, Un, kappa, dims, 0), n=1)
+    finally:
+        oracle.set_threads(nthr)
+    triad = oracle.triad_gbps()
+    what = ("the same right-hand side" if nrhs == 1 else
+            f"right-hand side 0 of the {nrhs}, the batch costed as {nrhs} sequential solves")
+    inner = "" if precision == 0 else " (the GPU's inner iterations in reduced precision; the oracle is FP64)"
+    return {
+        "value": 1.0 / (setup + per_iter * it_gpu),
+        "unit": "solves/s",
+        "cores": nthr,
+        "kind": "oracle",
+        "sample": f"FP64 oracle even-odd BiCGStab on {list(dims)}, {what}, run for 1 and {1 + k_it} "
+                  f"iterations ({one + more:.1f} s of CPU work); solve time = setup + per-iteration cost x "
+                  f"the {it_gpu:.0f} iterations the GPU solve needed{inner}",
+        "seconds_per_iteration": per_iter,
+        "setup_seconds": setup,
+        "units": {
+            "parity_hop_s": hop_s,
+            "parity_hop_gbs_algorithmic": (V // 2) * counts.hop_bytes_per_site("fp64") / hop_s / 1e9,
+            "parity_hop_one_thread_s": hop1_s,
+            "full_d_s": d_s,
+            "full_d_gflops": counts.FULL_D_FLOPS_PER_SITE * V / d_s / 1e9,
+            "host_triad_gbs": triad,
+        },
     }
 
 
@@ -262,6 +420,34 @@ def main():
         "gflops": counts.HOP_FLOPS_PER_SITE * Vh * nrhs / (d_us * 1e-6) / 1e9,
         "working_set_mb": d_bytes / max(d_n, 1) / 1e6,
     }
+
+    # ---- full D = 1 - kappa H on both parities (two hops, identity term fused); left out
+    # of --dslash-only runs, whose hop launches are then all plain parity hops ----
+    full_d = None
+    for _ in range(0 if args.dslash_only else 2):
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
+    torch.cuda.synchronize()
+    if not args.dslash_only:
+        L.wilson_timing_enable(ctx, True)
+        reps_d = max(args.dslash_reps // 2, 1)
+        for _ in range(reps_d):
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
+        torch.cuda.synchronize()
+        f_ms, f_n, f_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
+        L.wilson_timing_enable(ctx, False)
+        f_us = 1e3 * f_ms / reps_d
+        # the paper's count for D: each link, input and output read or written once per site
+        ideal_site = 4 * counts.link_bytes(lname) + nrhs * 2 * counts.spinor_site_bytes(sname)
+        full_d = {
+            "us_per_application": f_us,
+            "hop_launches_per_application": f_n / reps_d,
+            "gflops": counts.FULL_D_FLOPS_PER_SITE * V * nrhs / (f_us * 1e-6) / 1e9,
+            "ideal_bytes_per_site": ideal_site,
+            "gbs_ideal_count": ideal_site * V / (f_us * 1e-6) / 1e9,
+            "gbs_launch_count": f_bytes / (f_ms * 1e-3) / 1e9,
+        }
+    dslash["full_d"] = full_d
+    del out
 
     # ---- HBM reference: a plain streaming copy of 2 GiB (not the workload) ----
     nb = 1 << 31
@@ -357,35 +543,31 @@ def main():
                       "ms_per_batch": 1e3 * float(np.median(seq_t)),
                       "speedup_of_batched": (solves / total) / (nrhs / float(np.median(seq_t)))}
 
+    # ---- reduced-precision workloads: the same problem with the plain FP64 solver ----
+    fp64_same = None
+    if precision != 0:
+        f_lat, f_it = [], []
+        fopts = dict(opts, precision=0)
+        x.zero_()
+        L.check(L.wilson_solve_ex(ctx, g, x, srcs[0], nrhs, kap, tl, fopts)[0], "FP64 warm-up solve")
+        torch.cuda.synchronize()
+        nref = min(args.steps, 5)
+        for i in range(nref):
+            s0 = time.perf_counter()
+            st, info = L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, fopts)
+            f_lat.append(time.perf_counter() - s0)
+            L.check(st, "FP64 solve")
+            f_it.append(max(d["iterations"] for d in info))
+        f_val = nref * nrhs / sum(f_lat)
+        fp64_same = {"value": f_val, "unit": "solves/s", "p50_ms": 1e3 * percentile(f_lat, 50),
+                     "p99_ms": 1e3 * percentile(f_lat, 99), "iterations_median": float(np.median(f_it)),
+                     "solves": nref, "gain_solves_per_s": (solves / total) / f_val,
+                     "gain_p99": percentile(f_lat, 99) / percentile(lat, 99)}
+
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
-    if not args.no_cpu and nrhs == 1:
-        import oracle
-        Un = U.cpu().numpy()
-        bn = srcs[0].cpu().numpy()
-        # two runs of different length: their difference isolates the cost of an iteration
-        t1 = time.perf_counter()
-        oracle.solve(bn, Un, kappa, dims, 0.0, 1, "bicgstab_eo")
-        one = time.perf_counter() - t1
-        k_it = max(2, min(40, int(args.cpu_seconds / max(one, 1e-3))))
-        t1 = time.perf_counter()
-        oracle.solve(bn, Un, kappa, dims, 0.0, 1 + k_it, "bicgstab_eo")
-        more = time.perf_counter() - t1
-        per_iter = max(more - one, 1e-9) / k_it
-        setup = max(one - per_iter, 0.0)
-        it_per_solve = float(np.median(iters))
-        cpu = {
-            "value": 1.0 / (setup + per_iter * it_per_solve),
-            "unit": "solves/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle even-odd BiCGStab on the same {dims} problem, run for 1 and {1 + k_it} "
-                      f"iterations ({one + more:.1f} s of CPU work); solve time = setup + per-iteration cost x "
-                      f"the {it_per_solve:.0f} iterations the GPU solve needed",
-            "seconds_per_iteration": per_iter,
-            "setup_seconds": setup,
-        }
-        del Un
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)))
 
     line = {
         "metric": METRIC,
@@ -412,6 +594,7 @@ def main():
         "solve_hops": solve_hops,
         "cpu_baseline": cpu,
         "sequential_single_rhs": sequential,
+        "fp64_same_problem": fp64_same,
         "hbm_copy_gbs": copy_gbs,
         "hbm_read_gbs": read_gbs,
         "setup_s": setup_s,

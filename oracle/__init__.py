@@ -48,6 +48,7 @@ def _load():
                                         ctypes.c_int32, ctypes.c_int32, _dp]),
         "oracle_triad": (ctypes.c_double, [ctypes.c_int64, ctypes.c_int32]),
         "oracle_num_threads": (ctypes.c_int, []),
+        "oracle_set_threads": (None, [ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -229,3 +230,8 @@ def triad_gbps(n=1 << 26, reps=10):
 
 def num_threads():
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n):
+    """OpenMP threads for later oracle calls (timing only)."""
+    _load().oracle_set_threads(int(n))

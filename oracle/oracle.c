@@ -534,3 +534,7 @@ double oracle_triad(int64_t n, int32_t reps) {
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* OpenMP threads of later calls (for timing).  The operators write disjoint sites and do
+   not depend on it; the solver's OpenMP dot products may round differently. */
+void oracle_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -138,38 +138,37 @@ void *wilson_ctx::stage(DevBuf &b, size_t bytes) {
     return b.get();
 }
 
-void wilson_ctx::load_tune_cache() {
-    tune_loaded = true;
-    const char *env = std::getenv("WILSON_TUNE");
-    if (env && std::strcmp(env, "0") == 0) tune_enabled = false;
-    const char *fc = std::getenv("WILSON_HOP_CFG");
-    if (fc) {
-        forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d", &forced_cfg.block, &forced_cfg.rpt, &forced_cfg.xcd,
-                             &forced_cfg.zblk, &forced_cfg.lds_kb, &forced_cfg.wsplit) >= 4;
-    }
-    const char *path = std::getenv("WILSON_TUNE_CACHE");
-    if (!path || !*path) return;
-    tune_path = path;
-    std::ifstream in(tune_path);
-    std::string line;
-    // one JSON object per line: {"key": "...", "block": B, "rpt": R, "xcd": X, "ms": T}
-    while (std::getline(in, line)) {
-        const size_t k0 = line.find("\"key\": \"");
-        if (k0 == std::string::npos) continue;
-        const size_t k1 = line.find('"', k0 + 8);
-        if (k1 == std::string::npos) continue;
-        const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
-        LaunchCfg c;
-        if (std::sscanf(line.c_str() + k1,
-                        "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d",
-                        &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit) >= 5)
-            tuned[key] = c;
-    }
+TuneTable &tune_table() {
+    static TuneTable *t = [] {
+        TuneTable *T = new TuneTable();  // lives until the process ends
+        const char *env = std::getenv("WILSON_TUNE");
+        if (env && std::strcmp(env, "0") == 0) T->enabled = false;
+        const char *path = std::getenv("WILSON_TUNE_CACHE");
+        if (!path || !*path) return T;
+        T->path = path;
+        std::ifstream in(T->path);
+        std::string line;
+        // one JSON object per line: {"key": "...", "block": B, "rpt": R, "xcd": X, "zblk": Z, "lds_kb": K, "wsplit": W, "ms": T}
+        while (std::getline(in, line)) {
+            const size_t k0 = line.find("\"key\": \"");
+            if (k0 == std::string::npos) continue;
+            const size_t k1 = line.find('"', k0 + 8);
+            if (k1 == std::string::npos) continue;
+            const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
+            wl::LaunchCfg c;
+            if (std::sscanf(line.c_str() + k1,
+                            "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d",
+                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit) >= 5)
+                T->cfg[key] = c;
+        }
+        return T;
+    }();
+    return *t;
 }
 
-void wilson_ctx::save_tune_entry(const std::string &key, const LaunchCfg &c, double ms) {
-    if (tune_path.empty()) return;
-    std::ofstream out(tune_path, std::ios::app);
+void TuneTable::save(const std::string &key, const wl::LaunchCfg &c, double ms) {
+    if (path.empty()) return;
+    std::ofstream out(path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
         << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"wsplit\": " << c.wsplit
         << ", \"ms\": " << ms << "}\n";
@@ -177,11 +176,31 @@ void wilson_ctx::save_tune_entry(const std::string &key, const LaunchCfg &c, dou
 
 namespace wl {
 
+// Launches are tuned per lattice, precision pair, link storage and class of RHS count
+// (1, 2, 3-4, 5-8, 9+), not per epilogue or exact count: the best shape depends on the
+// streams, not on a fused dot or an added vector, and a finer key would re-tune for every
+// request size a server sees.
+static int rhs_class(int n) { return n <= 2 ? n : (n <= 4 ? 4 : (n <= 8 ? 8 : 12)); }
+
 static std::string hop_key(const HopArgs &a) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
     std::ostringstream os;
-    os << "hop sp=" << a.in.prec << " gp=" << a.gprec << " rc=" << a.recon << " nrhs=" << a.nrhs << " red=" << a.red << " y=" << a.has_y
+    os << "dev=" << dev << " hop sp=" << a.in.prec << " gp=" << a.gprec << " rc=" << a.recon << " rhs=" << rhs_class(a.nrhs)
        << " dims=" << a.g.L[0] << "x" << a.g.L[1] << "x" << a.g.L[2] << "x" << a.g.L[3];
     return os.str();
+}
+
+// A configuration made valid for this launch: the RHS split shrinks to a divisor of nrhs,
+// then the plane blocking, the wave split and the block size fall back if they still do not fit.
+static LaunchCfg fit_cfg(const HopArgs &a, LaunchCfg c) {
+    if (hop_cfg_valid(a, c)) return c;
+    while (c.rpt > 1 && (a.nrhs % c.rpt || (a.in.prec == P64 && c.rpt > 2))) c.rpt--;
+    if (c.zblk > 0 && a.g.L[2] % c.zblk) c.zblk = 0;
+    if (!hop_cfg_valid(a, c)) c.wsplit = 0;
+    if (!hop_cfg_valid(a, c)) c.block = 256;
+    if (!hop_cfg_valid(a, c)) c.rpt = 1;
+    return c;
 }
 
 static LaunchCfg default_cfg(const HopArgs &a) {
@@ -198,23 +217,28 @@ static LaunchCfg default_cfg(const HopArgs &a) {
 // its inputs, so repeated launches are harmless) and keep the fastest.
 static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
     std::vector<LaunchCfg> cands;
+    // plain block order once (the XCD-contiguous order has won every measured case), then
+    // the XCD order over block size, RHS split, plane blocking, LDS cap and wave split
+    {
+        LaunchCfg c = default_cfg(a);
+        c.xcd = 0;
+        cands.push_back(c);
+    }
     for (int wsplit : {0, 1})
         for (int block : {64, 128, 192, 256})
             for (int rpt : {1, 2, 3, 4})
-                for (int xcd : {0, 1})
-                    for (int zblk : {0, 4, 8})
-                        for (int lds_kb : {0, 24, 40, 56}) {
-                            if (xcd == 0 && (zblk != 0 || lds_kb != 0)) continue;
-                            if (wsplit && a.nrhs == 1) continue;
-                            LaunchCfg c;
-                            c.block = block;
-                            c.rpt = rpt;
-                            c.xcd = xcd;
-                            c.zblk = zblk;
-                            c.lds_kb = lds_kb;
-                            c.wsplit = wsplit;
-                            if (hop_cfg_valid(a, c)) cands.push_back(c);
-                        }
+                for (int zblk : {0, 4, 8})
+                    for (int lds_kb : {0, 40}) {
+                        if (wsplit && a.nrhs == 1) continue;
+                        LaunchCfg c;
+                        c.block = block;
+                        c.rpt = rpt;
+                        c.xcd = 1;
+                        c.zblk = zblk;
+                        c.lds_kb = lds_kb;
+                        c.wsplit = wsplit;
+                        if (hop_cfg_valid(a, c)) cands.push_back(c);
+                    }
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
@@ -251,28 +275,33 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
     if (a.nrhs < 1 || a.nrhs > kMaxRhs) throw Error(WILSON_INVALID_ARG, "nrhs out of range");
     if (a.out.data == a.in.data || (a.has_y && a.out.data == a.y.data) || (a.has_z && a.out.data == a.z.data))
         throw Error(WILSON_INVALID_ARG, "hop output aliases an input");
-    if (!ctx->tune_loaded) ctx->load_tune_cache();
+    if (!ctx->cfg_read) {
+        ctx->cfg_read = true;
+        const char *fc = std::getenv("WILSON_HOP_CFG");
+        if (fc) {
+            LaunchCfg &c = ctx->forced_cfg;
+            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit) >= 4;
+        }
+    }
+    TuneTable &T = tune_table();
     const std::string key = hop_key(a);
     LaunchCfg cfg;
-    auto it = ctx->tuned.find(key);
-    if (ctx->forced) {
-        cfg = ctx->forced_cfg;
-        if (!hop_cfg_valid(a, cfg)) {  // keep the pinned order and block, fit the RHS split
-            cfg.rpt = default_cfg(a).rpt;
-            if (cfg.zblk > 0 && a.g.L[2] % cfg.zblk) cfg.zblk = 0;
-            if (!hop_cfg_valid(a, cfg)) cfg.wsplit = 0;
-            if (!hop_cfg_valid(a, cfg)) cfg.block = 256;
+    {
+        std::lock_guard<std::mutex> lk(T.mu);
+        auto it = T.cfg.find(key);
+        if (ctx->forced) {
+            cfg = fit_cfg(a, ctx->forced_cfg);  // keep the pinned order and block, fit the RHS split
+        } else if (it != T.cfg.end()) {
+            cfg = fit_cfg(a, it->second);
+        } else if (T.enabled && a.g.Vh >= 4096) {
+            double ms = 0;
+            cfg = tune_hop(ctx, a, &ms);
+            T.cfg[key] = cfg;
+            T.save(key, cfg, ms);
+        } else {
+            cfg = default_cfg(a);
+            T.cfg[key] = cfg;
         }
-    } else if (it != ctx->tuned.end() && hop_cfg_valid(a, it->second)) {
-        cfg = it->second;
-    } else if (ctx->tune_enabled && a.g.Vh >= 4096) {
-        double ms = 0;
-        cfg = tune_hop(ctx, a, &ms);
-        ctx->tuned[key] = cfg;
-        ctx->save_tune_entry(key, cfg, ms);
-    } else {
-        cfg = default_cfg(a);
-        ctx->tuned[key] = cfg;
     }
     ctx->hop_launch_count++;
     if (ctx->timing) {

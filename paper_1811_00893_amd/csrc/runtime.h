@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -89,6 +90,22 @@ struct wilson_gauge {
     const void *links(int prec) const { return U[prec].get(); }
 };
 
+// Hop launch configurations chosen by the autotuner, shared by every context of the
+// process (a configuration is a property of the device and the launch shape).
+//   WILSON_TUNE=0                       no tuning: built-in default configuration
+//   WILSON_HOP_CFG="block,rpt,xcd,zblk[,lds_kb[,wsplit]]"   pin every hop launch of a context
+//                                       created after it is set (tests)
+//   WILSON_TUNE_CACHE=path              JSON lines read at start, new entries appended
+//   WILSON_TUNE_VERBOSE=1               print every timed candidate
+struct TuneTable {
+    std::mutex mu;
+    std::map<std::string, wl::LaunchCfg> cfg;
+    bool enabled = true;
+    std::string path;
+    void save(const std::string &key, const wl::LaunchCfg &c, double ms);
+};
+TuneTable &tune_table();
+
 struct wilson_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -102,6 +119,10 @@ struct wilson_ctx {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
+    // pinned hop configuration (WILSON_HOP_CFG), read at the context's first hop launch
+    bool cfg_read = false;
+    bool forced = false;
+    wl::LaunchCfg forced_cfg;
     double t_ms[WILSON_KERNEL_COUNT] = {0, 0};
     int64_t launches[WILSON_KERNEL_COUNT] = {0, 0};
     double t_bytes[WILSON_KERNEL_COUNT] = {0, 0};
@@ -110,15 +131,6 @@ struct wilson_ctx {
     hipEvent_t get_event();
     void drain_timing();  // resolves pending event pairs (waits for them)
 
-    // ---- autotuner ----
-    std::map<std::string, wl::LaunchCfg> tuned;
-    bool tune_enabled = true;
-    bool forced = false;   // WILSON_HOP_CFG="block,rpt,xcd,zblk[,lds_kb[,wsplit]]" pins every hop launch (tests)
-    wl::LaunchCfg forced_cfg;
-    bool tune_loaded = false;
-    std::string tune_path;
-    void load_tune_cache();
-    void save_tune_entry(const std::string &key, const wl::LaunchCfg &c, double ms);
 
     // ---- scratch ----
     wl::DevBuf stage_in, stage_out;  // canonical staging for host pointers

@@ -9,7 +9,7 @@
 
 Usage:
   python -m paper_1811_00893_amd.profiling stats --dir D --out F --command "..."
-  python -m paper_1811_00893_amd.profiling traffic --workload W --fetch D1 --write D2 --out F --command "..."
+  python -m paper_1811_00893_amd.profiling traffic --workload W --fetch D1 --write D2 --out F --command "..." [--first N]
 """
 import argparse
 import csv
@@ -48,21 +48,25 @@ def stats(d, out, command, top=14):
     return text
 
 
-def _counter(d, kernel_substr):
+def _counter(d, kernel_substr, first):
+    """Mean counter value over the first `first` dispatches of the kernel (bench.py's
+    plain hop loop; the full-D launches that follow carry an extra input), and over the
+    copy probe's dispatches."""
     rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
-    kern = [float(r["Counter_Value"]) for r in rows if kernel_substr in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    hits = [r for r in rows if kernel_substr in r["Kernel_Name"]][:first]
+    kern = [float(r["Counter_Value"]) for r in hits]
     copy = [float(r["Counter_Value"]) for r in rows if "stream_copy_kernel" in r["Kernel_Name"]]
     if not kern or not copy:
         raise ValueError(f"{d}: kernel '{kernel_substr}' or the copy probe not found")
-    name = [r["Kernel_Name"] for r in rows if kernel_substr in r["Kernel_Name"]][0]
-    return sum(kern) / len(kern), len(kern), sum(copy) / len(copy), name
+    return sum(kern) / len(kern), len(kern), sum(copy) / len(copy), hits[0]["Kernel_Name"]
 
 
-def traffic(workload, fetch_dir, write_dir, out, command, kernel_substr="hop_kernel"):
+def traffic(workload, fetch_dir, write_dir, out, command, first, kernel_substr="hop_kernel"):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench  # the hash of the kernel sources the counters describe
-    f_kib, nf, f_copy_kib, name = _counter(fetch_dir, kernel_substr)
-    w_kib, nw, w_copy_kib, _ = _counter(write_dir, kernel_substr)
+    f_kib, nf, f_copy_kib, name = _counter(fetch_dir, kernel_substr, first)
+    w_kib, nw, w_copy_kib, _ = _counter(write_dir, kernel_substr, first)
     f_scale = COPY_BYTES / (f_copy_kib * 1024)   # bytes read per FETCH_SIZE byte
     w_scale = COPY_BYTES / (w_copy_kib * 1024)   # bytes written per WRITE_SIZE byte
     rec = {
@@ -98,11 +102,13 @@ def main():
     b.add_argument("--write", required=True)
     b.add_argument("--out", required=True)
     b.add_argument("--command", required=True)
+    b.add_argument("--first", type=int, default=8,
+                   help="plain-hop dispatches at the start (bench.py: 3 warm-up + --dslash-reps)")
     args = p.parse_args()
     if args.cmd == "stats":
         print(stats(args.dir, args.out, args.command))
     else:
-        print(json.dumps(traffic(args.workload, args.fetch, args.write, args.out, args.command), indent=1))
+        print(json.dumps(traffic(args.workload, args.fetch, args.write, args.out, args.command, args.first), indent=1))
 
 
 if __name__ == "__main__":

@@ -7,8 +7,9 @@ time.  Each resident gauge field gets one batch of `nslots` solve slots in the l
     batch as soon as one frees up (a request may be partly running while the rest of its
     right-hand sides wait); a new batch is created only if its device footprint fits in
     the HBM budget next to everything already resident;
-  * enqueues `step_iters` iterations on every batch with running slots (all streams are
+  * enqueues a turn of iterations on every batch with running slots (all streams are
     fed before any is waited on, so batches of different lattices overlap on the GPU);
+    with `turn_ms` the iterations per turn adapt so that a turn lasts about that long;
   * polls every batch, copies finished solutions out and frees their slots;
   * completes a request when all its right-hand sides are done, recording latency
     from arrival to solution-on-host.
@@ -57,11 +58,14 @@ class Request:
 class Scheduler:
     """Admission, slot assignment, stepping and retirement (engine-agnostic)."""
 
-    def __init__(self, engine, hbm_budget: float, nslots: int = 12, step_iters: int = 8, clock=time.perf_counter):
+    def __init__(self, engine, hbm_budget: float, nslots: int = 12, step_iters: int = 8, clock=time.perf_counter,
+                 turn_ms: Optional[float] = None):
         self.engine = engine
         self.budget = float(hbm_budget)
         self.nslots = nslots
-        self.step_iters = step_iters
+        self.step_iters = step_iters   # iterations per turn (the maximum when turn_ms is set)
+        self.turn_ms = turn_ms         # target wall time of a turn: iterations adapt to it
+        self.iters = step_iters
         self.clock = clock
         self.gauges: Dict[Any, dict] = {}      # gauge_id -> {"dims", "bytes"}
         self.batches: Dict[Any, dict] = {}     # gauge_id -> {"handle", "slots": [(req, k) | None], "bytes"}
@@ -136,8 +140,9 @@ class Scheduler:
 
     def step(self):
         active = [b for b in self.batches.values() if any(s is not None for s in b["slots"])]
+        t0 = time.perf_counter()
         for b in active:                       # enqueue on every stream first ...
-            self.engine.step(b["handle"], self.step_iters)
+            self.engine.step(b["handle"], self.iters)
         for b in active:                       # ... then wait on each
             state, status = self.engine.poll(b["handle"])
             for k, slot in enumerate(b["slots"]):
@@ -154,6 +159,13 @@ class Scheduler:
                     self.engine.finish(req)
                     req.finish = self.clock()
                     self.completed.append(req)
+        if self.turn_ms and active:
+            # A slot whose Krylov cycle ends inside a turn waits for the turn to end before
+            # its next cycle starts, so turns are kept short: a few milliseconds of work,
+            # which on large lattices means polling every iteration or two.
+            ms = 1e3 * (time.perf_counter() - t0)
+            scale = self.turn_ms / max(ms, 1e-3)
+            self.iters = int(min(self.step_iters, max(1, round(self.iters * min(max(scale, 0.5), 2.0)))))
 
     def busy(self):
         return bool(self.waiting) or any(any(s is not None for s in b["slots"]) for b in self.batches.values())
@@ -236,6 +248,6 @@ class LibEngine:
         self.gauge.clear()
 
 
-def make_server(hbm_budget, nslots=12, step_iters=8, precision=1, solver=0):
+def make_server(hbm_budget, nslots=12, step_iters=8, precision=1, solver=0, turn_ms=None):
     eng = LibEngine(precision=precision, solver=solver)
-    return Scheduler(eng, hbm_budget, nslots=nslots, step_iters=step_iters), eng
+    return Scheduler(eng, hbm_budget, nslots=nslots, step_iters=step_iters, turn_ms=turn_ms), eng

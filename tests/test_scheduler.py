@@ -144,3 +144,32 @@ def test_result_independent_of_mix():
     a = run(0)
     b = run(5)
     assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+def test_turn_length_adapts_to_target():
+    """With a target turn duration the iterations per turn shrink when a turn runs long
+    and grow back (up to the maximum) when it runs short."""
+    import time as _time
+
+    class SlowEngine(FakeEngine):
+        per_iter_s = 0.002
+
+        def step(self, h, iters):
+            super().step(h, iters)
+            _time.sleep(iters * self.per_iter_s)
+
+    eng = SlowEngine()
+    sch = Scheduler(eng, hbm_budget=1e9, nslots=2, step_iters=16, clock=Clock(), turn_ms=8.0)
+    sch.register_gauge("g", (4, 4, 4, 4), 1)
+    sch.submit(mkreq(0, "g", 2, kappa=0.2))  # 200+ iterations
+    for _ in range(8):
+        sch.admit()
+        sch.step()
+    assert 2 <= sch.iters <= 6, sch.iters      # about 8 ms / 2 ms per iteration
+    eng.per_iter_s = 0.0001
+    for _ in range(8):
+        sch.admit()
+        sch.step()
+    assert sch.iters == 16                     # short turns: back to the maximum
+    sch.run_until_idle()
+    assert len(sch.completed) == 1
