@@ -146,6 +146,7 @@ struct LaunchCfg {
     int zblk = 0;      // >0: visit (z,t) planes in blocks of zblk z-values, t inner (divides Lz)
     int lds_kb = 0;    // >0: reserve this much LDS per block to cap blocks per CU (waves in flight)
     int wsplit = 0;    // 1: the waves of a block take successive RHS groups of the same 64 sites
+    int shx = 0;       // 1: x/y neighbours shuffled from the lanes that loaded them (RPT <= 2)
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----

@@ -11,6 +11,7 @@ hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
 // ---------------------------------------------------------------------------------
 bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
     if (c.rpt < 1 || c.rpt > 4) return false;
+    if (c.shx && c.rpt > 2) return false;
     if (a.nrhs % c.rpt != 0) return false;
     if (c.wsplit) {
         // 2..4 waves, each on its own RHS group of one 64-site tile

@@ -82,9 +82,39 @@ __device__ __forceinline__ constexpr bool spin_needed(int s) {
 
 // NE: stored complex entries per link (9, or 6 = the first two rows of an SU(3) matrix).
 // sgn: boundary sign of this hop (only used with NE == 6; full links carry it folded in).
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD>
+// Projected half spinor of one neighbour: gamma5 (when it acts on the input), the spin
+// projection of direction MU/FWD, and the FP16 site scale.
+template <int SP, int MU, bool FWD, bool G5>
+__device__ __forceinline__ void proj_in(const Cx<real_t<SP>> (&comp)[12], real_t<SP> sc, Cx<real_t<SP>> (&h)[2][3]) {
+    using R = real_t<SP>;
+    Cx<R> p[4][3];
+    // gamma5 on the input: (g5 psi)_s = -psi_{s^2} (a compile-time choice: the values
+    // of both permutations would otherwise have to stay live across a branch)
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if constexpr (G5)
+                p[sp][c] = spin_needed<MU, FWD>(sp) ? Cx<R>{-comp[(sp ^ 2) * 3 + c].re, -comp[(sp ^ 2) * 3 + c].im}
+                                                    : Cx<R>{R(0), R(0)};
+            else
+                p[sp][c] = spin_needed<MU, FWD>(sp) ? comp[sp * 3 + c] : Cx<R>{R(0), R(0)};
+        }
+    project<MU, FWD, R>(p, h);
+    if constexpr (SP == P16) {
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) h[k][c] = cscale(h[k][c], sc);
+    }
+}
+
+// SRC selects where the neighbour comes from: 0 = loaded here from the input field;
+// 1 = its projected half spinors given in H.
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD, int SRC = 0>
 __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
-                                        int r0, int nbr, int link_par, int link_site, real_t<SP> sgn, int stride) {
+                                        int r0, int nbr, int link_par, int link_site, real_t<SP> sgn, int stride,
+                                        const Cx<real_t<SP>> (*H)[2][3] = nullptr) {
     using R = real_t<SP>;
     // link U_mu(x) (forward, at the output site) or U_mu(x - mu) (backward, at the neighbour)
     Cx<R> U[3][3];
@@ -116,42 +146,26 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
     for (int r = 0; r < RPT; r++) {
         // with one RHS per lane the kernel has already returned when it is inactive
         if (RPT > 1 && !act[r]) continue;
-        const unsigned soff = (unsigned)nbr * 16u;
-        Cx<R> comp[12];
-#pragma unroll
-        for (int e = 0; e < NEL; e++) {
-            const bool need = half < 0 || ((e + 1) * CPE > 6 * half && e * CPE < 6 * half + 6);
-            if (need) ld_elem<SP, R>(&comp[e * CPE], splane(a.in.data, (r0 + r) * NEL + e, stride), soff);
-            else
-#pragma unroll
-                for (int k = 0; k < CPE; k++) comp[e * CPE + k] = {R(0), R(0)};
-        }
-        Cx<R> p[4][3];
-        // gamma5 on the input: (g5 psi)_s = -psi_{s^2} (a compile-time choice: the values
-        // of both permutations would otherwise have to stay live across a branch)
-        if constexpr (G5) {
-#pragma unroll
-            for (int sp = 0; sp < 4; sp++)
-#pragma unroll
-                for (int c = 0; c < 3; c++)
-                    p[sp][c] = spin_needed<MU, FWD>(sp)
-                                   ? Cx<R>{-comp[(sp ^ 2) * 3 + c].re, -comp[(sp ^ 2) * 3 + c].im}
-                                   : Cx<R>{R(0), R(0)};
-        } else {
-#pragma unroll
-            for (int sp = 0; sp < 4; sp++)
-#pragma unroll
-                for (int c = 0; c < 3; c++)
-                    p[sp][c] = spin_needed<MU, FWD>(sp) ? comp[sp * 3 + c] : Cx<R>{R(0), R(0)};
-        }
         Cx<R> h[2][3];
-        project<MU, FWD, R>(p, h);
-        if constexpr (SP == P16) {
-            const R sc = (R)a.in.scale[(size_t)(r0 + r) * stride + nbr];
+        if constexpr (SRC == 0) {
+            const unsigned soff = (unsigned)nbr * 16u;
+            Cx<R> comp[12];
+#pragma unroll
+            for (int e = 0; e < NEL; e++) {
+                const bool need = half < 0 || ((e + 1) * CPE > 6 * half && e * CPE < 6 * half + 6);
+                if (need) ld_elem<SP, R>(&comp[e * CPE], splane(a.in.data, (r0 + r) * NEL + e, stride), soff);
+                else
+#pragma unroll
+                    for (int k = 0; k < CPE; k++) comp[e * CPE + k] = {R(0), R(0)};
+            }
+            R sc = R(1);
+            if constexpr (SP == P16) sc = (R)a.in.scale[(size_t)(r0 + r) * stride + nbr];
+            proj_in<SP, MU, FWD, G5>(comp, sc, h);
+        } else {
 #pragma unroll
             for (int k = 0; k < 2; k++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) h[k][c] = cscale(h[k][c], sc);
+                for (int c = 0; c < 3; c++) h[k][c] = H[r][k][c];
         }
         Cx<R> u[2][3];
 #pragma unroll
@@ -175,7 +189,65 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
 
 // One output site i (all RPT right-hand sides of this lane): gather, project, multiply,
 // reconstruct, epilogue, store; the site's reduction terms are added to red[r][*].
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT>
+// Input components of site j (all RPT right-hand sides, raw: before gamma5 and FP16 scale).
+template <int SP, int RPT>
+__device__ __forceinline__ void load_raw(Cx<real_t<SP>> (&v)[RPT][12], real_t<SP> (&vs)[RPT], const HopArgs &a,
+                                         const bool (&act)[RPT], int r0, int j, int stride) {
+    using R = real_t<SP>;
+    constexpr int CPE = SpinorPack<SP>::CPE, NEL = SpinorPack<SP>::NEL;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        if (RPT > 1 && !act[r]) {  // defined values for the lanes' exchanges; never used
+#pragma unroll
+            for (int k = 0; k < 12; k++) v[r][k] = {R(0), R(0)};
+            vs[r] = R(1);
+            continue;
+        }
+#pragma unroll
+        for (int e = 0; e < NEL; e++)
+            ld_elem<SP, R>(&v[r][e * CPE], splane(a.in.data, (r0 + r) * NEL + e, stride), (unsigned)j * 16u);
+        if constexpr (SP == P16) vs[r] = (R)a.in.scale[(size_t)(r0 + r) * stride + j];
+        else vs[r] = R(1);
+    }
+}
+
+// Projected neighbour j (direction MU/FWD) of this lane's site i: every lane projects its
+// own centre C, and the lane of the same wavefront that holds site j as its centre
+// (lane + j - i) hands its result over; where no lane holds j (the neighbour belongs to
+// another wavefront, or the visiting order is not contiguous there) it is loaded.
+template <int SP, int RPT, int MU, bool FWD, bool G5>
+__device__ __forceinline__ void lane_nbr(Cx<real_t<SP>> (&H)[RPT][2][3], const Cx<real_t<SP>> (&C)[RPT][12],
+                                         const real_t<SP> (&Cs)[RPT], const HopArgs &a, const bool (&act)[RPT], int r0,
+                                         int i, int j, int stride) {
+    using R = real_t<SP>;
+    const int lane = (int)threadIdx.x & 63;
+    const int src = lane + (j - i);
+    const int srcc = src < 0 ? 0 : (src > 63 ? 63 : src);
+    const bool ok = src == srcc && __shfl(i, srcc, 64) == j;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        Cx<R> own[2][3];
+        proj_in<SP, MU, FWD, G5>(C[r], Cs[r], own);
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                H[r][k][c].re = __shfl(own[k][c].re, srcc, 64);
+                H[r][k][c].im = __shfl(own[k][c].im, srcc, 64);
+            }
+    }
+    if (!ok) {
+        Cx<R> v[RPT][12];
+        R vs[RPT];
+        load_raw<SP, RPT>(v, vs, a, act, r0, j, stride);
+#pragma unroll
+        for (int r = 0; r < RPT; r++) proj_in<SP, MU, FWD, G5>(v[r], vs[r], H[r]);
+    }
+    // the direction's link loads stay after the exchange (registers)
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX>
 __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, int r0, const bool (&act)[RPT],
                                          double (&red)[RPT][3]) {
     using R = real_t<SP>;
@@ -204,10 +276,27 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     const R one = R(1);
     const R sgn_tf = (NE == 6 && c.t == g.L[3] - 1) ? -one : one;  // forward hop across t = Lt-1 -> 0
     const R sgn_tb = (NE == 6 && c.t == 0) ? -one : one;            // backward hop across t = 0 -> Lt-1
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true>(acc, a, act, r0, xp, par, i, one, stride);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false>(acc, a, act, r0, xm, opar, xm, one, stride);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true>(acc, a, act, r0, yp, par, i, one, stride);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false>(acc, a, act, r0, ym, opar, ym, one, stride);
+    if constexpr (SHX) {
+        // the x-neighbours (one of them has this site's own index) and the y-neighbours
+        // are mostly the centres of lanes of the same wavefront
+        Cx<R> C[RPT][12];
+        R Cs[RPT];
+        load_raw<SP, RPT>(C, Cs, a, act, r0, i, stride);
+        Cx<R> H[RPT][2][3];
+        lane_nbr<SP, RPT, 0, true, G5>(H, C, Cs, a, act, r0, i, xp, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 1>(acc, a, act, r0, xp, par, i, one, stride, H);
+        lane_nbr<SP, RPT, 0, false, G5>(H, C, Cs, a, act, r0, i, xm, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 1>(acc, a, act, r0, xm, opar, xm, one, stride, H);
+        lane_nbr<SP, RPT, 1, true, G5>(H, C, Cs, a, act, r0, i, yp, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 1>(acc, a, act, r0, yp, par, i, one, stride, H);
+        lane_nbr<SP, RPT, 1, false, G5>(H, C, Cs, a, act, r0, i, ym, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 1>(acc, a, act, r0, ym, opar, ym, one, stride, H);
+    } else {
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true>(acc, a, act, r0, xp, par, i, one, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false>(acc, a, act, r0, xm, opar, xm, one, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true>(acc, a, act, r0, yp, par, i, one, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false>(acc, a, act, r0, ym, opar, ym, one, stride);
+    }
     hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true>(acc, a, act, r0, zp, par, i, one, stride);
     hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false>(acc, a, act, r0, zm, opar, zm, one, stride);
     hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true>(acc, a, act, r0, tp, par, i, sgn_tf, stride);
@@ -278,7 +367,7 @@ struct HopOcc {
     static constexpr int value = SP == P64 ? 2 : (RPT <= 2 ? 4 : 3);
 };
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT>
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<SP, RPT>::value)))
 hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     const Geom &g = a.g;
@@ -310,7 +399,7 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
 
     const bool valid = l < g.Vh;
     const int i = valid ? visit_order(l, g, vo) : g.Vh - 1;
-    hop_site<SP, GP, RPT, NE, G5, LNT>(a, i, valid, r0, act, red);
+    hop_site<SP, GP, RPT, NE, G5, LNT, SHX>(a, i, valid, r0, act, red);
 
     const int nv = red_nvals(a.red);
     if (nv == 0) return;
@@ -336,7 +425,7 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     }
 }
 
-template <int SP, int GP, int NE, bool G5, bool LNT>
+template <int SP, int GP, int NE, bool G5, bool LNT, bool SHX>
 static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const int ngroups = a.nrhs / c.rpt;
     dim3 grid(hop_nblocks(a, c) * (c.wsplit ? ngroups / (c.block / 64) : ngroups));
@@ -353,13 +442,17 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
         vo.zb = make_fastdiv((uint32_t)c.zblk);
     }
     switch (c.rpt) {
-        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
-        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
+        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
         case 3:
-            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 3, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            if constexpr (SP != P64 && !SHX)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 3, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            else return hipErrorInvalidValue;
             break;
         case 4:
-            if constexpr (SP != P64) hipLaunchKernelGGL((hop_kernel<SP, GP, 4, NE, G5, LNT>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            if constexpr (SP != P64 && !SHX)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 4, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            else return hipErrorInvalidValue;
             break;
         default: return hipErrorInvalidValue;
     }
@@ -370,8 +463,9 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
 // is read once per launch) and through L2 otherwise.
 template <int SP, int GP, int NE, bool G5>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
-    if (a.nrhs == c.rpt) return launch_hop_k<SP, GP, NE, G5, true>(a, c, s);
-    return launch_hop_k<SP, GP, NE, G5, false>(a, c, s);
+    const bool lnt = a.nrhs == c.rpt;
+    if (c.shx) return lnt ? launch_hop_k<SP, GP, NE, G5, true, true>(a, c, s) : launch_hop_k<SP, GP, NE, G5, false, true>(a, c, s);
+    return lnt ? launch_hop_k<SP, GP, NE, G5, true, false>(a, c, s) : launch_hop_k<SP, GP, NE, G5, false, false>(a, c, s);
 }
 
 template <int SP, int GP>

@@ -157,8 +157,9 @@ TuneTable &tune_table() {
             const std::string key = line.substr(k0 + 8, k1 - k0 - 8);
             wl::LaunchCfg c;
             if (std::sscanf(line.c_str() + k1,
-                            "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d",
-                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit) >= 5)
+                            "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d, "
+                            "\"shx\": %d",
+                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit, &c.shx) >= 5)
                 T->cfg[key] = c;
         }
         return T;
@@ -171,7 +172,7 @@ void TuneTable::save(const std::string &key, const wl::LaunchCfg &c, double ms) 
     std::ofstream out(path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
         << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"wsplit\": " << c.wsplit
-        << ", \"ms\": " << ms << "}\n";
+        << ", \"shx\": " << c.shx << ", \"ms\": " << ms << "}\n";
 }
 
 namespace wl {
@@ -195,7 +196,7 @@ static std::string hop_key(const HopArgs &a) {
 // then the plane blocking, the wave split and the block size fall back if they still do not fit.
 static LaunchCfg fit_cfg(const HopArgs &a, LaunchCfg c) {
     if (hop_cfg_valid(a, c)) return c;
-    while (c.rpt > 1 && (a.nrhs % c.rpt || (a.in.prec == P64 && c.rpt > 2))) c.rpt--;
+    while (c.rpt > 1 && (a.nrhs % c.rpt || (a.in.prec == P64 && c.rpt > 2) || (c.shx && c.rpt > 2))) c.rpt--;
     if (c.zblk > 0 && a.g.L[2] % c.zblk) c.zblk = 0;
     if (!hop_cfg_valid(a, c)) c.wsplit = 0;
     if (!hop_cfg_valid(a, c)) c.block = 256;
@@ -224,21 +225,23 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         c.xcd = 0;
         cands.push_back(c);
     }
-    for (int wsplit : {0, 1})
-        for (int block : {64, 128, 192, 256})
-            for (int rpt : {1, 2, 3, 4})
-                for (int zblk : {0, 4, 8})
-                    for (int lds_kb : {0, 40}) {
-                        if (wsplit && a.nrhs == 1) continue;
-                        LaunchCfg c;
-                        c.block = block;
-                        c.rpt = rpt;
-                        c.xcd = 1;
-                        c.zblk = zblk;
-                        c.lds_kb = lds_kb;
-                        c.wsplit = wsplit;
-                        if (hop_cfg_valid(a, c)) cands.push_back(c);
-                    }
+    for (int shx : {0, 1})
+        for (int wsplit : {0, 1})
+            for (int block : {64, 128, 192, 256})
+                for (int rpt : {1, 2, 3, 4})
+                    for (int zblk : {0, 4, 8})
+                        for (int lds_kb : {0, 40}) {
+                            if (wsplit && a.nrhs == 1) continue;
+                            LaunchCfg c;
+                            c.block = block;
+                            c.rpt = rpt;
+                            c.xcd = 1;
+                            c.zblk = zblk;
+                            c.lds_kb = lds_kb;
+                            c.wsplit = wsplit;
+                            c.shx = shx;
+                            if (hop_cfg_valid(a, c)) cands.push_back(c);
+                        }
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
@@ -258,8 +261,8 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         WL_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
         if (std::getenv("WILSON_TUNE_VERBOSE"))
-            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d: %.2f us\n", hop_key(a).c_str(),
-                         c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, c.wsplit, per * 1e3);
+            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d shx=%d: %.2f us\n", hop_key(a).c_str(),
+                         c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, c.wsplit, c.shx, per * 1e3);
         if (per < bms) {
             bms = per;
             best = c;
@@ -280,7 +283,8 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
         const char *fc = std::getenv("WILSON_HOP_CFG");
         if (fc) {
             LaunchCfg &c = ctx->forced_cfg;
-            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit) >= 4;
+            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit,
+                                      &c.shx) >= 4;
         }
     }
     TuneTable &T = tune_table();

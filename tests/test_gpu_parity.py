@@ -253,6 +253,32 @@ def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
             L.wilson_context_destroy(c)
 
 
+@pytest.mark.parametrize("cfg", ["256,1,1,0,0,0,1", "64,1,1,4,0,0,1"])
+def test_solves_with_lane_exchange(L, cfg, monkeypatch):
+    """Solves whose hops take x/y neighbours from other lanes: BiCGStab and CGNR (gamma5
+    on the hop input and output) in FP64, and mixed precision with FP16 spinors, all to
+    the oracle's residual test."""
+    monkeypatch.setenv("WILSON_HOP_CFG", cfg)
+    dims = (8, 8, 8, 8)
+    k, tol = 0.125, 1e-10
+    U = inputs.gauge_field(dims, eps=0.3, seed=1006)
+    b = inputs.gaussian_source(dims, seed=2006)
+    c = L.wilson_context_create()
+    g = L.wilson_gauge_load(c, U.to(DEV), dims, L.WILSON_GAUGE_FP32 | L.WILSON_GAUGE_FP16)
+    try:
+        for solver, prec in ((0, 0), (1, 0), (0, 2), (0, 3)):
+            x = torch.zeros_like(b, device=DEV)
+            st, info = L.wilson_solve_ex(c, g, x, b.to(DEV), 1, k, tol,
+                                         {"solver": solver, "precision": prec, "maxiter": 20000})
+            assert st == 0, (cfg, solver, prec, st, L.wilson_last_error())
+            res = oracle_residual(x.cpu().numpy(), b.numpy(), U.numpy(), k, dims)
+            print(f"{cfg} solver {solver} prec {prec}: {info[0]['iterations']} iterations, residual {res:.2e}")
+            assert res < tol
+    finally:
+        L.wilson_gauge_free(c, g)
+        L.wilson_context_destroy(c)
+
+
 def test_solve_edge_cases(L, ctx):
     dims = (4, 4, 2, 4)
     U, b = setup_case(dims, 8)
@@ -310,12 +336,15 @@ def test_full_size_sampled_dslash(L, ctx):
 
 
 @pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2",
-                                 "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1"])
+                                 "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1",
+                                 "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,2,1,0,0,1,1", "256,2,1,2,0,0,1"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
     XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
-    waves of a block) gives the oracle's result; the lattice has a ragged last block for
-    every block size."""
+    waves of a block, x/y neighbours exchanged between lanes) gives the oracle's result;
+    the lattice has a ragged last block for every block size, rows of 3 sites (x wraps
+    inside most wavefronts) and, with plane blocking, wavefronts whose sites are not
+    contiguous."""
     monkeypatch.setenv("WILSON_HOP_CFG", cfg)
     dims = (6, 4, 8, 10)  # Vh = 960: not a multiple of 64, 128 or 256
     U, _ = setup_case(dims, 9)
