@@ -1,11 +1,13 @@
-"""FP64 CPU oracle for the Wilson fermion matrix D = 1 - kappa*H and its solvers.
+"""FP64 CPU oracle for the Wilson fermion matrix D = 1 - kappa*H, the clover matrix
+D_clov = D + F, and their solvers.
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the CPU
 baseline leg of bench.py.  The product library never imports, links or calls it,
 and it shares no code with the GPU path.
 
 The arithmetic lives in oracle.c (Eq. (1) of Sec. 2.1 written out with dense 4x4
-gamma matrices on the full lattice).  This module adds ctypes marshalling and a
+gamma matrices on the full lattice; the clover term of Sec. 2.1.2 as a dense 12x12
+site matrix).  This module adds ctypes marshalling and a
 few numpy helpers that are definitions rather than algorithms: the parity mask,
 the dense matrix assembled column by column, and the FP16 per-site-scale codec.
 
@@ -49,6 +51,13 @@ def _load():
         "oracle_triad": (ctypes.c_double, [ctypes.c_int64, ctypes.c_int32]),
         "oracle_num_threads": (ctypes.c_int, []),
         "oracle_set_threads": (None, [ctypes.c_int32]),
+        "oracle_clover_inverse": (ctypes.c_int, [_dp, _dp, ctypes.c_int64]),
+        "oracle_apply_Dclov": (None, [_dp, _dp, _dp, _dp, ctypes.c_double, _i32p]),
+        "oracle_clov_eo_prepare": (None, [_dp, _dp, _dp, _dp, ctypes.c_double, _i32p]),
+        "oracle_clov_eo_reconstruct": (None, [_dp, _dp, _dp, _dp, ctypes.c_double, _i32p]),
+        "oracle_apply_Mee_clov": (None, [_dp, _dp, _dp, _dp, ctypes.c_double, _i32p, ctypes.c_int32]),
+        "oracle_solve_clov": (ctypes.c_int, [_dp, _dp, _dp, _dp, ctypes.c_double, _i32p, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.c_int32, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -185,6 +194,73 @@ def solve(b, U, kappa, dims, tol, maxiter, method="bicgstab_eo", x0=None):
     tr = ctypes.c_double(0.0)
     st = _load().oracle_solve(_ptr(x), _ptr(b), _ptr(U), float(kappa), d.ctypes.data_as(_i32p), float(tol),
                               int(maxiter), METHODS[method], ctypes.byref(tr))
+    return x, int(st), float(tr.value)
+
+
+# ---- clover fermion matrix (Sec. 2.1.2): D_clov = D_W + F(x) delta_{x,y} ----
+# F is an input array (V, 12, 12) complex128, Hermitian per site, rows and columns
+# 3*spin + colour in the Dirac basis.
+
+def _clover(F, V):
+    F = np.ascontiguousarray(F, dtype=np.complex128)
+    assert F.size == 144 * V, F.shape
+    return F
+
+
+def clover_inverse(F):
+    """(1 + F(x))^-1 per site, (V, 12, 12); raises if a site matrix is singular."""
+    F = np.ascontiguousarray(F, dtype=np.complex128)
+    V = F.size // 144
+    out = np.empty((V, 12, 12), np.complex128)
+    if _load().oracle_clover_inverse(_ptr(out), _ptr(F), V) != 0:
+        raise ValueError("singular 1 + F")
+    return out
+
+
+def apply_Dclov(psi, U, F, kappa, dims):
+    """D_clov psi = (1 + F) psi - kappa H psi."""
+    d = _dims(dims); V = volume(d)
+    psi = _spinor(psi, V); U = _links(U, V); F = _clover(F, V)
+    out = np.empty((V, 4, 3), np.complex128)
+    _load().oracle_apply_Dclov(_ptr(out), _ptr(psi), _ptr(U), _ptr(F), float(kappa), d.ctypes.data_as(_i32p))
+    return out
+
+
+def clov_eo_prepare(b, U, F, kappa, dims):
+    """b'_e = b_e + kappa H_eo T_oo^-1 b_o on even sites (odd sites 0)."""
+    d = _dims(dims); V = volume(d)
+    b = _spinor(b, V); U = _links(U, V); F = _clover(F, V)
+    out = np.empty((V, 4, 3), np.complex128)
+    _load().oracle_clov_eo_prepare(_ptr(out), _ptr(b), _ptr(U), _ptr(F), float(kappa), d.ctypes.data_as(_i32p))
+    return out
+
+
+def clov_eo_reconstruct(x_even, b, U, F, kappa, dims):
+    """x with x_o = T_oo^-1 (b_o + kappa H_oe x_e) written on the odd sites."""
+    d = _dims(dims); V = volume(d)
+    x = _spinor(x_even, V).copy(); b = _spinor(b, V); U = _links(U, V); F = _clover(F, V)
+    _load().oracle_clov_eo_reconstruct(_ptr(x), _ptr(b), _ptr(U), _ptr(F), float(kappa), d.ctypes.data_as(_i32p))
+    return x.reshape(V, 4, 3)
+
+
+def apply_Mee_clov(psi, U, F, kappa, dims, dagger=False):
+    """M_ee psi_e = T_ee psi_e - kappa^2 H_eo T_oo^-1 H_oe psi_e (odd sites of psi ignored)."""
+    d = _dims(dims); V = volume(d)
+    psi = _spinor(psi, V); U = _links(U, V); F = _clover(F, V)
+    out = np.empty((V, 4, 3), np.complex128)
+    _load().oracle_apply_Mee_clov(_ptr(out), _ptr(psi), _ptr(U), _ptr(F), float(kappa), d.ctypes.data_as(_i32p),
+                                  int(bool(dagger)))
+    return out
+
+
+def solve_clov(b, U, F, kappa, dims, tol, maxiter, method="bicgstab_eo"):
+    """Solve D_clov x = b; returns (x, status, true_rel_residual) as solve()."""
+    d = _dims(dims); V = volume(d)
+    b = _spinor(b, V); U = _links(U, V); F = _clover(F, V)
+    x = np.zeros((V, 4, 3), np.complex128)
+    tr = ctypes.c_double(0.0)
+    st = _load().oracle_solve_clov(_ptr(x), _ptr(b), _ptr(U), _ptr(F), float(kappa), d.ctypes.data_as(_i32p),
+                                   float(tol), int(maxiter), METHODS[method], ctypes.byref(tr))
     return x, int(st), float(tr.value)
 
 

@@ -512,6 +512,258 @@ int oracle_bicgstab_fixed(double *x, const double *b, const double *U, double ka
     return oracle_solve(x, b, U, kappa, dims, 0.0, iters, method, &tr);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Clover fermion matrix (Sec. 2.1.2):  D_clov = D_W + F(x) delta_{x,y},        */
+/* F(x) a Hermitian 12x12 site matrix made of link variables and stored as an  */
+/* array like U; the paper does not give its construction, so F is an input:   */
+/* F[s][a][b], a, b = 3*spin + colour (Dirac basis), complex.  With            */
+/* T(x) = 1 + F(x) the site-diagonal block, D_clov psi = T psi - kappa H psi.  */
+/* Even-odd: D_clov = [[T_ee, -k H_eo], [-k H_oe, T_oo]] gives                 */
+/*   M_ee = T_ee - k^2 H_eo T_oo^-1 H_oe,  b'_e = b_e + k H_eo T_oo^-1 b_o,     */
+/*   x_o = T_oo^-1 (b_o + k H_oe x_e).                                          */
+/* Written literally: dense 12x12 products and a dense inverse per site.      */
+/* ------------------------------------------------------------------------- */
+
+/* out = M v for a dense 12x12 M (row-major) and a 12-vector v. */
+static void mat12_vec(cplx *out, const cplx *M, const cplx *v) {
+    for (int a = 0; a < 12; a++) {
+        cplx acc = 0;
+        for (int b = 0; b < 12; b++) acc += M[a * 12 + b] * v[b];
+        out[a] = acc;
+    }
+}
+
+/* Inverse of a 12x12 complex matrix by Gauss-Jordan elimination with partial
+   pivoting.  Returns 0, or -1 if a pivot is zero. */
+static int mat12_inverse(cplx *inv, const cplx *M) {
+    cplx a[12][24];
+    for (int r = 0; r < 12; r++)
+        for (int c = 0; c < 24; c++) a[r][c] = c < 12 ? M[r * 12 + c] : (c - 12 == r ? 1.0 : 0.0);
+    for (int col = 0; col < 12; col++) {
+        int piv = col;
+        for (int r = col + 1; r < 12; r++)
+            if (cabs(a[r][col]) > cabs(a[piv][col])) piv = r;
+        if (cabs(a[piv][col]) == 0.0) return -1;
+        if (piv != col)
+            for (int c = 0; c < 24; c++) {
+                cplx t = a[col][c];
+                a[col][c] = a[piv][c];
+                a[piv][c] = t;
+            }
+        cplx d = a[col][col];
+        for (int c = 0; c < 24; c++) a[col][c] /= d;
+        for (int r = 0; r < 12; r++) {
+            if (r == col) continue;
+            cplx f = a[r][col];
+            if (f == 0) continue;
+            for (int c = 0; c < 24; c++) a[r][c] -= f * a[col][c];
+        }
+    }
+    for (int r = 0; r < 12; r++)
+        for (int c = 0; c < 12; c++) inv[r * 12 + c] = a[r][12 + c];
+    return 0;
+}
+
+/* Tinv[s] = (1 + F[s])^-1 on every site.  Returns -1 if some T is singular. */
+int oracle_clover_inverse(double *Tinv, const double *F, int64_t V) {
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long s = 0; s < V; s++) {
+        cplx T[144];
+        const cplx *f = (const cplx *)F + s * 144;
+        for (int k = 0; k < 144; k++) T[k] = f[k] + ((k / 12 == k % 12) ? 1.0 : 0.0);
+        bad |= mat12_inverse((cplx *)Tinv + s * 144, T) != 0;
+    }
+    return bad ? -1 : 0;
+}
+
+/* out(s) = M(s) in(s) on sites of parity `which` (2: all); M = T (inv = 0), with
+   T = 1 + F, or the given inverses (inv = 1, M = Tinv).  out may alias in. */
+static void site_apply(cplx *out, const cplx *in, const cplx *F, const cplx *Tinv, int inv, const int L[4],
+                       int which) {
+    long V = volume(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        if (which != 2 && site_parity(s, L) != which) continue;
+        cplx v[12], r[12];
+        memcpy(v, in + s * 12, sizeof v);
+        if (inv) {
+            mat12_vec(r, Tinv + s * 144, v);
+        } else {
+            mat12_vec(r, F + s * 144, v);
+            for (int k = 0; k < 12; k++) r[k] += v[k];
+        }
+        memcpy(out + s * 12, r, sizeof r);
+    }
+}
+
+/* D_clov psi = (1 + F) psi - kappa H psi on all sites. */
+void oracle_apply_Dclov(double *out, const double *psi, const double *U, const double *F, double kappa,
+                        const int32_t dims[4]) {
+    int L[4] = {dims[0], dims[1], dims[2], dims[3]};
+    long V = volume(L);
+    cplx *tp = malloc(sizeof(cplx) * 12 * V);
+    site_apply(tp, (const cplx *)psi, (const cplx *)F, NULL, 0, L, 2);
+    hop_axpy((cplx *)out, (const cplx *)psi, (const cplx *)U, L, 2, -kappa, tp, 1.0);
+    free(tp);
+}
+
+typedef struct {
+    const cplx *U, *F, *Tinv;
+    int L[4];
+    double kappa;
+    cplx *tmp, *tmp2;
+} clov_ctx;
+
+/* out_e = M_ee in_e = T_ee in_e - k^2 H_eo T_oo^-1 H_oe in_e (odd sites of out = 0). */
+static void apply_Mee_clov(cplx *out, const cplx *in, clov_ctx *c) {
+    long V = volume(c->L);
+    memset(c->tmp, 0, sizeof(cplx) * 12 * V);
+    hop_axpy(c->tmp, in, c->U, c->L, 1, 1.0, NULL, 0.0);          /* H_oe in_e */
+    site_apply(c->tmp, c->tmp, c->F, c->Tinv, 1, c->L, 1);          /* T_oo^-1 */
+    memset(c->tmp2, 0, sizeof(cplx) * 12 * V);
+    site_apply(c->tmp2, in, c->F, NULL, 0, c->L, 0);                /* T_ee in_e */
+    hop_axpy(out, c->tmp, c->U, c->L, 0, -c->kappa * c->kappa, c->tmp2, 1.0);
+    zero_parity(out, c->L, 1);
+}
+
+/* M_ee^dag = gamma5 M_ee gamma5, valid when F commutes with gamma5 (F block diagonal
+   in the chiral basis, as the inputs are built). */
+static void apply_Mee_clov_dagger(cplx *out, const cplx *in, clov_ctx *c) {
+    long V = volume(c->L);
+    cplx *g = malloc(sizeof(cplx) * 12 * V);
+    oracle_gamma5((double *)g, (const double *)in, V);
+    apply_Mee_clov(out, g, c);
+    oracle_gamma5((double *)g, (const double *)out, V);
+    memcpy(out, g, sizeof(cplx) * 12 * V);
+    free(g);
+}
+
+static void clov_prepare(cplx *bp, const cplx *b, clov_ctx *c) {
+    long V = volume(c->L);
+    memset(c->tmp, 0, sizeof(cplx) * 12 * V);
+    site_apply(c->tmp, b, c->F, c->Tinv, 1, c->L, 1);                 /* T_oo^-1 b_o */
+    memset(bp, 0, sizeof(cplx) * 12 * V);
+    hop_axpy(bp, c->tmp, c->U, c->L, 0, c->kappa, b, 1.0);            /* b_e + k H_eo (.) */
+}
+
+static void clov_reconstruct(cplx *x, const cplx *b, clov_ctx *c) {
+    long V = volume(c->L);
+    cplx *xe = malloc(sizeof(cplx) * 12 * V);
+    memcpy(xe, x, sizeof(cplx) * 12 * V);
+    zero_parity(xe, c->L, 1);
+    hop_axpy(x, xe, c->U, c->L, 1, c->kappa, b, 1.0);                 /* b_o + k H_oe x_e */
+    site_apply(x, x, c->F, c->Tinv, 1, c->L, 1);                      /* T_oo^-1 */
+    free(xe);
+}
+
+static int clov_ctx_init(clov_ctx *c, const double *U, const double *F, double kappa, const int32_t dims[4]) {
+    c->U = (const cplx *)U;
+    c->F = (const cplx *)F;
+    memcpy(c->L, dims, sizeof c->L);
+    c->kappa = kappa;
+    long V = volume(c->L);
+    c->tmp = malloc(sizeof(cplx) * 12 * V);
+    c->tmp2 = malloc(sizeof(cplx) * 12 * V);
+    cplx *ti = malloc(sizeof(cplx) * 144 * V);
+    c->Tinv = ti;
+    return oracle_clover_inverse((double *)ti, F, V);
+}
+
+static void clov_ctx_free(clov_ctx *c) {
+    free(c->tmp);
+    free(c->tmp2);
+    free((void *)c->Tinv);
+}
+
+void oracle_clov_eo_prepare(double *bprime, const double *b, const double *U, const double *F, double kappa,
+                            const int32_t dims[4]) {
+    clov_ctx c;
+    clov_ctx_init(&c, U, F, kappa, dims);
+    clov_prepare((cplx *)bprime, (const cplx *)b, &c);
+    clov_ctx_free(&c);
+}
+
+void oracle_clov_eo_reconstruct(double *x, const double *b, const double *U, const double *F, double kappa,
+                                const int32_t dims[4]) {
+    clov_ctx c;
+    clov_ctx_init(&c, U, F, kappa, dims);
+    clov_reconstruct((cplx *)x, (const cplx *)b, &c);
+    clov_ctx_free(&c);
+}
+
+void oracle_apply_Mee_clov(double *out, const double *in, const double *U, const double *F, double kappa,
+                           const int32_t dims[4], int32_t dagger) {
+    clov_ctx c;
+    clov_ctx_init(&c, U, F, kappa, dims);
+    long V = volume(c.L);
+    cplx *ine = malloc(sizeof(cplx) * 12 * V);
+    memcpy(ine, in, sizeof(cplx) * 12 * V);
+    zero_parity(ine, c.L, 1);
+    if (dagger)
+        apply_Mee_clov_dagger((cplx *)out, ine, &c);
+    else
+        apply_Mee_clov((cplx *)out, ine, &c);
+    free(ine);
+    clov_ctx_free(&c);
+}
+
+static void op_Dclov(cplx *out, const cplx *in, void *vctx) {
+    clov_ctx *c = vctx;
+    long V = volume(c->L);
+    site_apply(c->tmp2, in, c->F, NULL, 0, c->L, 2);
+    hop_axpy(out, in, c->U, c->L, 2, -c->kappa, c->tmp2, 1.0);
+    (void)V;
+}
+static void op_Mee_clov(cplx *out, const cplx *in, void *vctx) { apply_Mee_clov(out, in, vctx); }
+static void op_Mee_clov_dag(cplx *out, const cplx *in, void *vctx) { apply_Mee_clov_dagger(out, in, vctx); }
+
+/* Solve D_clov x = b; methods and return values as oracle_solve.  Returns -3 if
+   some site matrix 1 + F is singular. */
+int oracle_solve_clov(double *x, const double *b, const double *U, const double *F, double kappa,
+                      const int32_t dims[4], double tol, int32_t maxiter, int32_t method, double *true_res) {
+    clov_ctx c;
+    if (clov_ctx_init(&c, U, F, kappa, dims) != 0) {
+        clov_ctx_free(&c);
+        return -3;
+    }
+    long V = volume(c.L);
+    long n = 12 * V;
+    const cplx *bb = (const cplx *)b;
+    cplx *xx = (cplx *)x;
+    double bnorm = sqrt(norm2(bb, n));
+    int ret;
+    double res;
+    if (bnorm == 0.0) {
+        memset(x, 0, sizeof(cplx) * n);
+        if (true_res) *true_res = 0.0;
+        clov_ctx_free(&c);
+        return 0;
+    }
+    if (method == 0) {
+        ret = bicgstab(xx, bb, n, op_Dclov, &c, tol, bnorm, maxiter, &res);
+    } else {
+        cplx *bp = malloc(sizeof(cplx) * n);
+        clov_prepare(bp, bb, &c);
+        zero_parity(xx, c.L, 1);
+        if (method == 1)
+            ret = bicgstab(xx, bp, n, op_Mee_clov, &c, tol, bnorm, maxiter, &res);
+        else
+            ret = cgls(xx, bp, n, op_Mee_clov, op_Mee_clov_dag, &c, tol, bnorm, maxiter, &res);
+        clov_reconstruct(xx, bb, &c);
+        free(bp);
+    }
+    if (true_res) {
+        cplx *r = malloc(sizeof(cplx) * n);
+        op_Dclov(r, xx, &c);
+        for (long i = 0; i < n; i++) r[i] = bb[i] - r[i];
+        *true_res = sqrt(norm2(r, n)) / bnorm;
+        free(r);
+    }
+    clov_ctx_free(&c);
+    return ret;
+}
+
 /* |a - b| relative helpers for tests */
 double oracle_norm(const double *a, int64_t n_complex) { return sqrt(norm2((const cplx *)a, n_complex)); }
 

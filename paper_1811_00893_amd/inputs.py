@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs: SU(3) gauge fields and spinor sources.
+"""Seeded synthetic inputs: SU(3) gauge fields, clover terms and spinor sources.
 
 This module holds input generators only, none of the Wilson operator's or the
 solvers' arithmetic; both the GPU path and the CPU oracle are fed from it.
@@ -70,6 +70,32 @@ def unit_gauge(dims, device="cpu"):
     U[..., 1, 1] = 1
     U[..., 2, 2] = 1
     return U
+
+
+def _gamma5_dirac():
+    """gamma_5 of the Dirac basis used throughout (gamma_k = [[0,-i s_k],[i s_k,0]],
+    gamma_4 = diag(1,1,-1,-1)): the 4x4 matrix -[[0,1],[1,0]] in 2x2 spin blocks."""
+    g5 = np.zeros((4, 4))
+    g5[0, 2] = g5[1, 3] = g5[2, 0] = g5[3, 1] = -1.0
+    return g5
+
+
+def clover_field(dims, c=0.05, seed=1201, device="cpu"):
+    """Synthetic clover term F(x), shape (V, 12, 12) complex128 (rows and columns
+    3*spin + colour, Dirac basis).  The paper builds F from the links and stores it
+    like U without giving the construction; a stand-in with its structure is:
+    F = c (P+ G1 P+ + P- G2 P-), P+- = (1 +- gamma_5)/2 (x) 1_colour, G1, G2 Hermitian
+    with Gaussian entries (G = (M + M^dag)/2, M with N(0,1) real and imaginary parts),
+    so F is Hermitian and commutes with gamma_5, i.e. block diagonal with two 6x6
+    Hermitian blocks in the chiral basis.  c = 0.05 keeps |F| near 0.25."""
+    V = volume(dims)
+    M = _gaussian_complex((V, 2, 12, 12), seed, device)
+    G = 0.5 * (M + M.conj().transpose(-1, -2))
+    g5 = torch.from_numpy(np.kron(_gamma5_dirac(), np.eye(3))).to(G.device, torch.complex128)
+    eye = torch.eye(12, dtype=torch.complex128, device=G.device)
+    Pp, Pm = 0.5 * (eye + g5), 0.5 * (eye - g5)
+    F = c * (Pp @ G[:, 0] @ Pp + Pm @ G[:, 1] @ Pm)
+    return F
 
 
 def random_su3(n, seed, eps=2.0, device="cpu"):
