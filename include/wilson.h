@@ -151,8 +151,34 @@ int wilson_context_destroy(wilson_ctx *ctx);
 int wilson_gauge_load(wilson_ctx *ctx, wilson_gauge **g, const double *U, const int32_t dims[4],
                       uint32_t precisions);
 int wilson_gauge_free(wilson_ctx *ctx, wilson_gauge *g);
-/* Device bytes held by a resident gauge field. */
+/* Device bytes held by a resident gauge field (links and any clover term). */
 size_t wilson_gauge_bytes(const wilson_gauge *g);
+
+/*
+ * Clover term (Sec. 2.1.2 of the paper): the clover fermion matrix adds a site term,
+ * D_clov(x,y) = D(x,y) + F(x) delta_{x,y}, with F(x) a Hermitian 12x12 matrix that is
+ * block diagonal, two Hermitian 6x6 blocks, in the chiral basis (equivalently: F
+ * commutes with gamma5).  The paper stores F like the links and does not build it; the
+ * caller supplies it.
+ *
+ * wilson_gauge_attach_clover attaches F to a resident gauge field.  From then on every
+ * call on g uses D_clov: wilson_dslash_ex with parity 2 applies D_clov (parity 0/1 is the
+ * off-diagonal block -kappa*H, common to both matrices); wilson_solve_ex and the batch
+ * API solve D_clov x = b (even-odd: M_ee = T_ee - kappa^2 H_eo T_oo^-1 H_oe with
+ * T = 1 + F, x_o = T_oo^-1 (b_o + kappa H_oe x_e)), in every precision and solver.
+ *   F: V x 12 x 12 complex doubles (interleaved re, im), F[s][a][b] at complex offset
+ *      (s*12 + a)*12 + b, site s in canonical order, a, b = 3*spin + colour in the
+ *      library's Dirac basis (gamma5 = -[[0,1],[1,0]] on the spin pairs (0,2), (1,3));
+ *      host or device; read during the call only.
+ * The library keeps T and T^-1 per site as packed chiral blocks in FP64 and FP32
+ * (1728 bytes per site).  Attaching again replaces the term.
+ * Errors: INVALID_ARG (NULL; F not Hermitian or not commuting with gamma5 beyond a
+ * relative 1e-12; T singular at some site), OUT_OF_MEMORY, DEVICE_ERROR; on error the
+ * field keeps its previous state.
+ */
+int wilson_gauge_attach_clover(wilson_ctx *ctx, wilson_gauge *g, const double *F);
+/* Remove the clover term: g is a plain Wilson field again. */
+int wilson_gauge_detach_clover(wilson_ctx *ctx, wilson_gauge *g);
 
 /*
  * Dslash on a resident gauge field, for nrhs fields stored back to back (canonical

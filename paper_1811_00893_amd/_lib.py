@@ -38,7 +38,8 @@ EXPORTS = [
     "wilson_gauge_free", "wilson_gauge_bytes", "wilson_dslash_ex", "wilson_solve_ex", "wilson_footprint_bytes",
     "wilson_batch_create", "wilson_batch_destroy", "wilson_batch_attach", "wilson_batch_step", "wilson_batch_poll",
     "wilson_batch_detach", "wilson_timing_enable", "wilson_timing_read", "wilson_stream_copy", "wilson_strerror",
-    "wilson_last_error", "wilson_version", "wilson_stream_read",
+    "wilson_last_error", "wilson_version", "wilson_stream_read", "wilson_gauge_attach_clover",
+    "wilson_gauge_detach_clover",
 ]
 
 
@@ -68,6 +69,8 @@ _SIGS = {
     "wilson_gauge_load": (_i32, [_vp, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_uint32]),
     "wilson_gauge_free": (_i32, [_vp, _vp]),
     "wilson_gauge_bytes": (ctypes.c_size_t, [_vp]),
+    "wilson_gauge_attach_clover": (_i32, [_vp, _vp, _vp]),
+    "wilson_gauge_detach_clover": (_i32, [_vp, _vp]),
     "wilson_dslash_ex": (_i32, [_vp, _vp, _vp, _vp, _d, _i32, _i32, _i32]),
     "wilson_solve_ex": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(wilson_solve_opts),
                                ctypes.POINTER(wilson_solve_info)]),
@@ -223,6 +226,16 @@ def wilson_gauge_free(ctx, g):
 
 def wilson_gauge_bytes(g):
     return int(lib().wilson_gauge_bytes(g))
+
+
+def wilson_gauge_attach_clover(ctx, g, F, dims):
+    """Attach the clover term F (V x 12 x 12 complex128, canonical) to gauge field g."""
+    _check_size(F, _dims(dims), 1, "F", per_site=288)
+    return lib().wilson_gauge_attach_clover(ctx, g, _ptr(F))
+
+
+def wilson_gauge_detach_clover(ctx, g):
+    return check(lib().wilson_gauge_detach_clover(ctx, g), "wilson_gauge_detach_clover")
 
 
 def wilson_dslash_ex(ctx, g, out, in_, kappa, parity, precision=WILSON_FP64, nrhs=1):

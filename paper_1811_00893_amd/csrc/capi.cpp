@@ -234,6 +234,47 @@ int wilson_gauge_free(wilson_ctx *ctx, wilson_gauge *g) {
 
 size_t wilson_gauge_bytes(const wilson_gauge *g) { return g ? g->bytes() : 0; }
 
+int wilson_gauge_attach_clover(wilson_ctx *ctx, wilson_gauge *g, const double *F) {
+    API_BEGIN
+    WL_CHECK_ARG(ctx != nullptr && g != nullptr && F != nullptr, "ctx / g / F is NULL");
+    const size_t V = (size_t)g->dims[0] * g->dims[1] * g->dims[2] * g->dims[3];
+    DevBuf tmp;
+    Staged sf(ctx, tmp, F, V * 144 * 2 * sizeof(double), true);
+    DevBuf t[2], ti[2];
+    for (int p = 0; p < 2; p++) {
+        t[p].alloc(2 * clover_parity_bytes(p, g->g));
+        ti[p].alloc(2 * clover_parity_bytes(p, g->g));
+    }
+    if (ctx->flag.size() < sizeof(int)) ctx->flag.alloc(256);
+    static const int zero = 0;
+    WL_HIP(hipMemcpyAsync(ctx->flag.get(), &zero, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    WL_HIP(launch_clover_pack(t[P64].get(), ti[P64].get(), t[P32].get(), ti[P32].get(), sf.dev, g->g, 1e-12,
+                              ctx->flag.as<int>(), ctx->stream));
+    int bad = 0;
+    WL_HIP(hipMemcpyAsync(&bad, ctx->flag.get(), sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    if (bad & 1) throw Error(WILSON_INVALID_ARG, "clover term F is not Hermitian or does not commute with gamma5");
+    if (bad & 2) throw Error(WILSON_INVALID_ARG, "clover term: 1 + F is singular at some site");
+    for (int p = 0; p < 2; p++) {
+        g->clovT[p] = std::move(t[p]);
+        g->clovTi[p] = std::move(ti[p]);
+    }
+    return WILSON_OK;
+    API_END
+}
+
+int wilson_gauge_detach_clover(wilson_ctx *ctx, wilson_gauge *g) {
+    API_BEGIN
+    WL_CHECK_ARG(ctx != nullptr && g != nullptr, "ctx / g is NULL");
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    for (int p = 0; p < 2; p++) {
+        g->clovT[p].release();
+        g->clovTi[p].release();
+    }
+    return WILSON_OK;
+    API_END
+}
+
 int wilson_dslash_ex(wilson_ctx *ctx, const wilson_gauge *g, double *out, const double *in, double kappa,
                      int32_t parity, int32_t precision, int32_t nrhs) {
     API_BEGIN

@@ -136,7 +136,28 @@ struct HopArgs {
     int pstride;       // stride between partial rows (0: the launch's block count)
     RhsState *state;   // optional: per-rhs phase gate
     int run_mask;
+    // clover site term (see ClovMode): packed 6x6 blocks of the output parity, in the
+    // precision of the arithmetic (FP64 for FP64 spinors, FP32 otherwise)
+    const void *clov;
+    int clov_mode;
 };
+
+// Where the clover site matrices (T = 1 + F or its inverse, packed per site as two
+// Hermitian 6x6 blocks of the chiral basis) enter a hop's epilogue.
+enum ClovMode {
+    CLV_NONE = 0,
+    CLV_Y = 1,    // out = cH H in + T y          (the reduction partner y stays y)
+    CLV_Z = 2,    // out = cH H in + y + cz T z
+    CLV_ALL = 3   // out = T (cH H in + y)        (T: the blocks passed, e.g. the inverse)
+};
+
+// Packed Hermitian 6x6 block: 6 real diagonal entries, then the 15 entries above the
+// diagonal (row-major) as (re, im): 36 reals; two blocks (+, - chirality) per site.
+constexpr int kClovReals = 72;
+// bytes of one parity's packed clover blocks (planes of 16-byte elements)
+__host__ __device__ inline size_t clover_parity_bytes(int prec, const Geom &g) {
+    return (size_t)(prec == P64 ? 36 : 18) * g.stride * 16u;
+}
 
 // Launch configuration chosen by the tuner.
 struct LaunchCfg {
@@ -146,7 +167,7 @@ struct LaunchCfg {
     int zblk = 0;      // >0: visit (z,t) planes in blocks of zblk z-values, t inner (divides Lz)
     int lds_kb = 0;    // >0: reserve this much LDS per block to cap blocks per CU (waves in flight)
     int wsplit = 0;    // 1: the waves of a block take successive RHS groups of the same 64 sites
-    int shx = 0;       // 1: x/y neighbours shuffled from the lanes that loaded them (RPT <= 2)
+    int shx = 0;       // 1: x/y neighbours shuffled from the lanes that loaded them (RPT 1)
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----
@@ -208,5 +229,14 @@ hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStrea
 hipError_t launch_stream_read(const void *src, size_t bytes, unsigned *sink, hipStream_t s);
 // Checks that canonical input is finite; sets *flag (device int) to 1 otherwise.
 hipError_t launch_check_finite(const double *p, size_t n, int *flag, hipStream_t s);
+// clover: canonical F (V x 12 x 12 complex, Dirac basis) -> packed T = 1 + F and T^-1 for
+// both parities in FP64 (and FP32 when t32/ti32 are given); flag |= 1 when F is not
+// Hermitian or does not commute with gamma5 (relative tolerance tol), |= 2 when a block
+// of T is singular.
+hipError_t launch_clover_pack(void *t64, void *ti64, void *t32, void *ti32, const double *F, const Geom &g,
+                              double tol, int *flag, hipStream_t s);
+// out = M in on one parity (M: packed blocks of that parity, in the spinors' precision
+// family), for nrhs right-hand sides.
+hipError_t launch_clover_apply(Spinor out, Spinor in, const void *blocks, const Geom &g, int nrhs, hipStream_t s);
 
 }  // namespace wl

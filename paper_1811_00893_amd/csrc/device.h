@@ -83,9 +83,11 @@ __host__ __device__ constexpr unsigned link_elem_bytes(int prec) { return prec =
 
 // plane addressing: a wave-uniform plane base plus one 32-bit per-lane byte offset, so the
 // loads of a site share one offset register and the bases stay in scalar registers
-// The plane base is passed through readfirstlane: it is uniform anyway, and without it the
-// compiler folds the lane offset into the base first and then adds each plane's offset
-// with a 64-bit per-lane multiply-add, instead of one scalar base per plane.
+// The plane base is passed through readfirstlane, so every caller must pass a base and a
+// plane index that are the same on all lanes of the wavefront (a kernel whose lanes may
+// belong to different fields or parities takes them from blockIdx, not from the lane).
+// Without it the compiler folds the lane offset into the base first and then adds each
+// plane's offset with a 64-bit per-lane multiply-add, instead of one scalar base per plane.
 __device__ __forceinline__ const char *uniform_ptr(const char *p) {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -222,6 +224,83 @@ __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, i
 #pragma unroll
         for (int e = 0; e < NEL; e++)
             st_elem<P, R>(const_cast<char *>(splane(f.data, r * NEL + e, stride)), off, &v[e * CPE]);
+    }
+}
+
+// ---- clover site term -----------------------------------------------------------
+// A site matrix T (12x12, commuting with gamma5) is kept as two Hermitian 6x6 blocks of
+// the chiral basis.  In this Dirac basis gamma5 = -[[0,1],[1,0]] on spin pairs, so with
+// d = v_up - v_lo and s = v_up + v_lo (spins (0,2) and (1,3), colour inner; the +
+// and - chirality components up to 1/sqrt 2):
+//     (T v)_up = (T+ d + T- s) / 2,   (T v)_lo = (T- s - T+ d) / 2.
+// Packed block: reals 0..5 the diagonal, then (re, im) of the 15 entries above the
+// diagonal in row-major order; element planes: block b, element e -> plane b*EPB + e.
+template <int P>
+struct ClovPack {
+    static constexpr int EPB = P == P64 ? 18 : 9;  // 16-byte elements per block
+};
+__host__ __device__ constexpr int herm6_off(int i, int j) { return 6 + 2 * (i * (11 - i) / 2 + (j - i - 1)); }
+
+template <int P, typename R>
+__device__ __forceinline__ void clov_load_block(R (&m)[36], const void *base, int blk, int stride, int i) {
+    constexpr int EPB = ClovPack<P>::EPB;
+    const unsigned off = (unsigned)i * 16u;
+#pragma unroll
+    for (int e = 0; e < EPB; e++) {
+        const char *pl = splane(base, blk * EPB + e, stride);
+        if constexpr (P == P64) {
+            const dvec2 v = *reinterpret_cast<const dvec2 *>(pl + off);
+            m[2 * e] = (R)v.x;
+            m[2 * e + 1] = (R)v.y;
+        } else {
+            const fvec4 v = *reinterpret_cast<const fvec4 *>(pl + off);
+            m[4 * e] = (R)v.x;
+            m[4 * e + 1] = (R)v.y;
+            m[4 * e + 2] = (R)v.z;
+            m[4 * e + 3] = (R)v.w;
+        }
+    }
+}
+
+// y = M x for a packed Hermitian 6x6 block M
+template <typename R>
+__device__ __forceinline__ void herm6_apply(Cx<R> (&y)[6], const R (&m)[36], const Cx<R> (&x)[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] = cscale(x[i], m[i]);
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = i + 1; j < 6; j++) {
+            const Cx<R> a = {m[herm6_off(i, j)], m[herm6_off(i, j) + 1]};
+            y[i] = cfma(y[i], a, x[j]);       // M_ij x_j
+            y[j] = cfma_conj(y[j], a, x[i]);  // M_ji x_i = conj(M_ij) x_i
+        }
+}
+
+// v <- T v for the site matrix whose packed blocks (storage precision P) start at base
+template <int P, typename R>
+__device__ __forceinline__ void clov_apply(Cx<R> (&v)[12], const void *base, int stride, int i) {
+    Cx<R> d[6], sm[6], yp[6], ym[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        d[k] = csub(v[k], v[k + 6]);
+        sm[k] = cadd(v[k], v[k + 6]);
+    }
+    {
+        R m[36];
+        clov_load_block<P, R>(m, base, 0, stride, i);
+        herm6_apply(yp, m, d);
+    }
+    {
+        R m[36];
+        clov_load_block<P, R>(m, base, 1, stride, i);
+        herm6_apply(ym, m, sm);
+    }
+    const R h = R(0.5);
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        v[k] = cscale(cadd(yp[k], ym[k]), h);
+        v[k + 6] = cscale(csub(ym[k], yp[k]), h);
     }
 }
 

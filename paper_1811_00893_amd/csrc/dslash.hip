@@ -11,7 +11,8 @@ hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
 // ---------------------------------------------------------------------------------
 bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
     if (c.rpt < 1 || c.rpt > 4) return false;
-    if (c.shx && c.rpt > 2) return false;
+    if (c.shx && c.rpt != 1) return false;  // with more RHS per lane the exchange spills
+    if (a.clov_mode != CLV_NONE && (c.rpt != 1 || c.shx)) return false;  // clover kernels: one RHS per lane
     if (a.nrhs % c.rpt != 0) return false;
     if (c.wsplit) {
         // 2..4 waves, each on its own RHS group of one 64-site tile

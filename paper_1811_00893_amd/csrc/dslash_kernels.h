@@ -247,7 +247,7 @@ __device__ __forceinline__ void lane_nbr(Cx<real_t<SP>> (&H)[RPT][2][3], const C
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX>
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV>
 __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, int r0, const bool (&act)[RPT],
                                          double (&red)[RPT][3]) {
     using R = real_t<SP>;
@@ -302,6 +302,7 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true>(acc, a, act, r0, tp, par, i, sgn_tf, stride);
     hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride);
 
+    constexpr int CP = SP == P64 ? P64 : P32;  // storage precision of clover blocks
 #pragma unroll
     for (int r = 0; r < RPT; r++) {
         if (RPT > 1 && !act[r]) continue;
@@ -319,12 +320,23 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
         Cx<R> yv[12];
         if (a.has_y) {
             load_site<SP, R>(yv, a.y, stride, rhs, i);
+            if (CLV && a.clov_mode == CLV_Y) {  // T y enters the sum; y itself stays the dot partner
+                Cx<R> ty[12];
 #pragma unroll
-            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], yv[k]);
+                for (int k = 0; k < 12; k++) ty[k] = yv[k];
+                clov_apply<CP, R>(ty, a.clov, stride, i);
+#pragma unroll
+                for (int k = 0; k < 12; k++) o[k] = cadd(o[k], ty[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; k++) o[k] = cadd(o[k], yv[k]);
+            }
         }
+        if (CLV && a.clov_mode == CLV_ALL) clov_apply<CP, R>(o, a.clov, stride, i);
         if (a.has_z) {
             Cx<R> zv[12];
             load_site<SP, R>(zv, a.z, stride, rhs, i);
+            if (CLV && a.clov_mode == CLV_Z) clov_apply<CP, R>(zv, a.clov, stride, i);
             const R cz = (R)a.cz;
 #pragma unroll
             for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
@@ -367,7 +379,7 @@ struct HopOcc {
     static constexpr int value = SP == P64 ? 2 : (RPT <= 2 ? 4 : 3);
 };
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX>
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<SP, RPT>::value)))
 hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     const Geom &g = a.g;
@@ -399,7 +411,7 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
 
     const bool valid = l < g.Vh;
     const int i = valid ? visit_order(l, g, vo) : g.Vh - 1;
-    hop_site<SP, GP, RPT, NE, G5, LNT, SHX>(a, i, valid, r0, act, red);
+    hop_site<SP, GP, RPT, NE, G5, LNT, SHX, CLV>(a, i, valid, r0, act, red);
 
     const int nv = red_nvals(a.red);
     if (nv == 0) return;
@@ -425,7 +437,7 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     }
 }
 
-template <int SP, int GP, int NE, bool G5, bool LNT, bool SHX>
+template <int SP, int GP, int NE, bool G5, bool LNT, bool SHX, bool CLV>
 static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const int ngroups = a.nrhs / c.rpt;
     dim3 grid(hop_nblocks(a, c) * (c.wsplit ? ngroups / (c.block / 64) : ngroups));
@@ -442,16 +454,20 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
         vo.zb = make_fastdiv((uint32_t)c.zblk);
     }
     switch (c.rpt) {
-        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
-        case 2: hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
+        case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, LNT, SHX, CLV>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
+        case 2:
+            if constexpr (!CLV && !SHX)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, LNT, SHX, CLV>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            else return hipErrorInvalidValue;
+            break;
         case 3:
-            if constexpr (SP != P64 && !SHX)
-                hipLaunchKernelGGL((hop_kernel<SP, GP, 3, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            if constexpr (SP != P64 && !SHX && !CLV)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 3, NE, G5, LNT, SHX, CLV>), grid, block, lds, s, a, remap, vo, c.wsplit);
             else return hipErrorInvalidValue;
             break;
         case 4:
-            if constexpr (SP != P64 && !SHX)
-                hipLaunchKernelGGL((hop_kernel<SP, GP, 4, NE, G5, LNT, SHX>), grid, block, lds, s, a, remap, vo, c.wsplit);
+            if constexpr (SP != P64 && !SHX && !CLV)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 4, NE, G5, LNT, SHX, CLV>), grid, block, lds, s, a, remap, vo, c.wsplit);
             else return hipErrorInvalidValue;
             break;
         default: return hipErrorInvalidValue;
@@ -464,8 +480,14 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
 template <int SP, int GP, int NE, bool G5>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const bool lnt = a.nrhs == c.rpt;
-    if (c.shx) return lnt ? launch_hop_k<SP, GP, NE, G5, true, true>(a, c, s) : launch_hop_k<SP, GP, NE, G5, false, true>(a, c, s);
-    return lnt ? launch_hop_k<SP, GP, NE, G5, true, false>(a, c, s) : launch_hop_k<SP, GP, NE, G5, false, false>(a, c, s);
+    if (a.clov_mode != CLV_NONE)  // clover epilogue: its own instantiations (one RHS per lane)
+        return lnt ? launch_hop_k<SP, GP, NE, G5, true, false, true>(a, c, s)
+                   : launch_hop_k<SP, GP, NE, G5, false, false, true>(a, c, s);
+    if (c.shx)
+        return lnt ? launch_hop_k<SP, GP, NE, G5, true, true, false>(a, c, s)
+                   : launch_hop_k<SP, GP, NE, G5, false, true, false>(a, c, s);
+    return lnt ? launch_hop_k<SP, GP, NE, G5, true, false, false>(a, c, s)
+               : launch_hop_k<SP, GP, NE, G5, false, false, false>(a, c, s);
 }
 
 template <int SP, int GP>

@@ -98,7 +98,9 @@ double hop_bytes(const HopArgs &a) {
     if (a.has_y) per_rhs += sb;
     if (a.has_z) per_rhs += sb;
     if (a.red == RED_DOT) per_rhs += sb;  // dot partner
-    return (double)a.g.Vh * (lb + a.nrhs * per_rhs);
+    // clover site blocks: 72 reals per site, read once for all right-hand sides
+    const double cb = a.clov_mode != CLV_NONE ? kClovReals * real_bytes(a.in.prec == P64 ? P64 : P32) : 0.0;
+    return (double)a.g.Vh * (lb + cb + a.nrhs * per_rhs);
 }
 
 }  // namespace wl
@@ -196,7 +198,11 @@ static std::string hop_key(const HopArgs &a) {
 // then the plane blocking, the wave split and the block size fall back if they still do not fit.
 static LaunchCfg fit_cfg(const HopArgs &a, LaunchCfg c) {
     if (hop_cfg_valid(a, c)) return c;
-    while (c.rpt > 1 && (a.nrhs % c.rpt || (a.in.prec == P64 && c.rpt > 2) || (c.shx && c.rpt > 2))) c.rpt--;
+    if (a.clov_mode != CLV_NONE) {
+        c.rpt = 1;
+        c.shx = 0;
+    }
+    while (c.rpt > 1 && (a.nrhs % c.rpt || (a.in.prec == P64 && c.rpt > 2) || c.shx)) c.rpt--;
     if (c.zblk > 0 && a.g.L[2] % c.zblk) c.zblk = 0;
     if (!hop_cfg_valid(a, c)) c.wsplit = 0;
     if (!hop_cfg_valid(a, c)) c.block = 256;
@@ -278,6 +284,7 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
     if (a.nrhs < 1 || a.nrhs > kMaxRhs) throw Error(WILSON_INVALID_ARG, "nrhs out of range");
     if (a.out.data == a.in.data || (a.has_y && a.out.data == a.y.data) || (a.has_z && a.out.data == a.z.data))
         throw Error(WILSON_INVALID_ARG, "hop output aliases an input");
+    if (a.clov_mode != CLV_NONE && a.clov == nullptr) throw Error(WILSON_INVALID_ARG, "clover blocks missing");
     if (!ctx->cfg_read) {
         ctx->cfg_read = true;
         const char *fc = std::getenv("WILSON_HOP_CFG");
@@ -307,6 +314,7 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
             T.cfg[key] = cfg;
         }
     }
+    cfg = fit_cfg(a, cfg);  // a shape stored for the key may not suit this launch (clover, RHS count)
     ctx->hop_launch_count++;
     if (ctx->timing) {
         hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();

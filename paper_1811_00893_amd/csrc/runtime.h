@@ -86,8 +86,21 @@ struct wilson_gauge {
     int32_t dims[4];
     wl::DevBuf U[3];  // per wl::Prec
     int recon = 18;   // 12: links stored as two rows (SU(3) verified at upload)
-    size_t bytes() const { return U[0].size() + U[1].size() + U[2].size(); }
+    // clover term (optional): packed T = 1 + F and T^-1 for both parities, FP64 and FP32
+    wl::DevBuf clovT[2], clovTi[2];
+    size_t bytes() const {
+        return U[0].size() + U[1].size() + U[2].size() + clovT[0].size() + clovT[1].size() + clovTi[0].size() +
+               clovTi[1].size();
+    }
     const void *links(int prec) const { return U[prec].get(); }
+    bool has_clover() const { return clovT[0].get() != nullptr; }
+    // blocks of parity par for spinors of precision prec (FP64 blocks for FP64, FP32 otherwise)
+    const void *clover(bool inverse, int prec, int par) const {
+        const int cp = prec == wl::P64 ? wl::P64 : wl::P32;
+        const wl::DevBuf &b = inverse ? clovTi[cp] : clovT[cp];
+        if (!b.get()) return nullptr;
+        return static_cast<const char *>(b.get()) + (size_t)par * wl::clover_parity_bytes(cp, g);
+    }
 };
 
 // Hop launch configurations chosen by the autotuner, shared by every context of the

@@ -151,17 +151,24 @@ class EoCore {
         for (int k = 0; k < nk; k++) h1.cH[k] = 1.0;
         h1.state = S(st);
         h1.run_mask = mask;
+        if (G->has_clover()) {  // tmp_o = T_oo^-1 H_oe in
+            h1.clov = G->clover(true, in.prec, 1);
+            h1.clov_mode = CLV_ALL;
+        }
         run_hop(h1);
         HopArgs h2 = hop_args(0, out, tmpo);
         if (bmx) {
             h2.has_y = 1; h2.y = V(*bmx);
             h2.has_z = 1; h2.z = V(in); h2.cz = -1.0;
             for (int k = 0; k < nk; k++) h2.cH[k] = kap(k) * kap(k);
+            if (G->has_clover()) h2.clov_mode = CLV_Z;  // b_e - T_ee in + k^2 H tmp
         } else {
             h2.has_y = 1; h2.y = V(in);
             h2.g5out = dag;
             for (int k = 0; k < nk; k++) h2.cH[k] = -kap(k) * kap(k);
+            if (G->has_clover()) h2.clov_mode = CLV_Y;  // T_ee in - k^2 H tmp (T commutes with g5)
         }
+        if (G->has_clover()) h2.clov = G->clover(false, in.prec, 0);
         h2.red = red;
         h2.w = V(w);
         h2.state = S(st);
@@ -216,17 +223,28 @@ class EoCore {
     }
 
     // b' = b_e + k H_eo b_o
+    // (clover: b'_e = b_e + k H_eo T_oo^-1 b_o)
     void prepare_bprime() {
-        HopArgs a = hop_args(0, bp.f, b_o.f);
+        Spinor src = b_o.f;
+        if (G->has_clover()) {
+            Spinor t = tmp64_or_scratch();
+            WL_HIP(launch_clover_apply(V(t), V(b_o.f), G->clover(true, P64, 1), g, nk, ctx->stream));
+            src = t;
+        }
+        HopArgs a = hop_args(0, bp.f, src);
         a.has_y = 1; a.y = V(b_e.f);
         for (int k = 0; k < nk; k++) a.cH[k] = kap(k);
         run_hop(a);
     }
-    // x_o = b_o + k H_oe x_e
+    // x_o = b_o + k H_oe x_e  (clover: x_o = T_oo^-1 (b_o + k H_oe x_e))
     void reconstruct() {
         HopArgs a = hop_args(1, x_o.f, x_e.f);
         a.has_y = 1; a.y = V(b_o.f);
         for (int k = 0; k < nk; k++) a.cH[k] = kap(k);
+        if (G->has_clover()) {
+            a.clov = G->clover(true, P64, 1);
+            a.clov_mode = CLV_ALL;
+        }
         run_hop(a);
     }
     // |b - D x|^2 of the full system into sout()[].aux (nothing stored)
@@ -237,6 +255,10 @@ class EoCore {
             a.has_y = 1; a.y = V(par ? b_o.f : b_e.f);
             a.has_z = 1; a.z = V(par ? x_o.f : x_e.f); a.cz = -1.0;
             for (int k = 0; k < nk; k++) a.cH[k] = kap(k);
+            if (G->has_clover()) {  // b - T x + k H x
+                a.clov = G->clover(false, P64, par);
+                a.clov_mode = CLV_Z;
+            }
             a.red = RED_NORM2;
             const int nb = run_hop(a);
             finalize(par ? FIN_ADD_AUX : FIN_STORE_AUX, 1, nb, sout(), kAllPhases);
@@ -628,9 +650,13 @@ void dslash_device(wilson_ctx *ctx, const wilson_gauge *G, double *out, const do
         a.gprec = P == P64 ? P64 : GP;
         a.recon = G->recon;
         for (int k = 0; k < nrhs; k++) a.cH[k] = -kappa;
-        if (parity == 2) {
+        if (parity == 2) {  // D psi = T psi - k H psi (T = 1 without a clover term)
             a.has_y = 1;
             a.y = par ? ws->in_o.f : ws->in_e.f;
+            if (G->has_clover()) {
+                a.clov = G->clover(false, P, par);
+                a.clov_mode = CLV_Y;
+            }
         }
         hop(ctx, a, hop_bytes(a));
         WL_HIP(launch_from_parity(out, a.out, g, par, nrhs, ctx->stream));

@@ -337,7 +337,7 @@ def test_full_size_sampled_dslash(L, ctx):
 
 @pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2",
                                  "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1",
-                                 "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,2,1,0,0,1,1", "256,2,1,2,0,0,1"])
+                                 "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,1,1,0,0,1,1", "256,1,1,2,0,0,1"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
     XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
