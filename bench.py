@@ -10,7 +10,8 @@ the dominant kernel (the parity hop, measured with HIP events on the library's s
 over the timed region) against the MI355X HBM peak, a Dslash-only figure (parity hop
 alone), and the CPU oracle timed on a bounded sample of the same workload.
 
-Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | batched24 | serve.
+Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | mixed48_fp16h |
+batched24 | clover32 | clover32_mixed | serve.
 """
 import argparse
 import json
@@ -87,7 +88,12 @@ WORKLOADS = {
                       "mixed precision (FP16 spinors + per-site scale, FP16 links inner; FP64 outer), 48^3x96"),
     "batched24": ((24, 24, 24, 48), 0.125, 1e-10, 1, 12,
                   "12 point sources in one batched solve, FP32 inner / FP64 outer, 24^3x48, kappa=0.125"),
+    "clover32": ((32, 32, 32, 64), 0.125, 1e-10, 0, 1,
+                 "clover matrix D_W + F, plain FP64 even-odd BiCGStab, 32^3x64, kappa=0.125, synthetic F (c=0.05)"),
+    "clover32_mixed": ((32, 32, 32, 64), 0.125, 1e-10, 1, 1,
+                       "clover matrix D_W + F, mixed precision (FP32 inner, FP64 outer), 32^3x64, kappa=0.125"),
 }
+CLOVER = {"clover32", "clover32_mixed"}
 
 
 def run_serving(args):
@@ -293,7 +299,7 @@ def run_serving(args):
     }
 
 
-def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu):
+def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None):
     """The FP64 oracle timed on the host: an even-odd BiCGStab solve (run for 1 and 1+k
     iterations, whose difference isolates the cost of an iteration, scaled to the number
     of iterations the GPU solve took), and the operator units (parity hop, full D) with
@@ -304,12 +310,19 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu):
     from paper_1811_00893_amd import counts
     Un = U.cpu().numpy()
     bn = (b[0] if nrhs > 1 else b).cpu().numpy()
+    Fn = None if F is None else F.cpu().numpy()
+
+    def solve(iters):
+        if Fn is None:
+            return oracle.solve(bn, Un, kappa, dims, 0.0, iters, "bicgstab_eo")
+        return oracle.solve_clov(bn, Un, Fn, kappa, dims, 0.0, iters, "bicgstab_eo")
+
     t1 = time.perf_counter()
-    oracle.solve(bn, Un, kappa, dims, 0.0, 1, "bicgstab_eo")
+    solve(1)
     one = time.perf_counter() - t1
     k_it = max(2, min(40, int(args.cpu_seconds / max(one, 1e-3))))
     t1 = time.perf_counter()
-    oracle.solve(bn, Un, kappa, dims, 0.0, 1 + k_it, "bicgstab_eo")
+    solve(1 + k_it)
     more = time.perf_counter() - t1
     per_iter = max(more - one, 1e-9) / k_it
     setup = max(one - per_iter, 0.0)
@@ -324,7 +337,10 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu):
         return min(ts)
 
     hop_s = best_of(lambda: oracle.dslash(bn, Un, kappa, dims, 0))
-    d_s = best_of(lambda: oracle.apply_D(bn, Un, kappa, dims))
+    if Fn is None:
+        d_s = best_of(lambda: oracle.apply_D(bn, Un, kappa, dims))
+    else:
+        d_s = best_of(lambda: oracle.apply_Dclov(bn, Un, Fn, kappa, dims))
     nthr = oracle.num_threads()
     oracle.set_threads(1)
     try:
@@ -340,7 +356,8 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu):
         "unit": "solves/s",
         "cores": nthr,
         "kind": "oracle",
-        "sample": f"FP64 oracle even-odd BiCGStab on {list(dims)}, {what}, run for 1 and {1 + k_it} "
+        "sample": f"FP64 oracle even-odd BiCGStab{' (clover matrix)' if Fn is not None else ''} on {list(dims)}, "
+                  f"{what}, run for 1 and {1 + k_it} "
                   f"iterations ({one + more:.1f} s of CPU work); solve time = setup + per-iteration cost x "
                   f"the {it_gpu:.0f} iterations the GPU solve needed{inner}",
         "seconds_per_iteration": per_iter,
@@ -350,7 +367,7 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu):
             "parity_hop_gbs_algorithmic": (V // 2) * counts.hop_bytes_per_site("fp64") / hop_s / 1e9,
             "parity_hop_one_thread_s": hop1_s,
             "full_d_s": d_s,
-            "full_d_gflops": counts.FULL_D_FLOPS_PER_SITE * V / d_s / 1e9,
+            "full_d_gflops": (counts.FULL_D_FLOPS_PER_SITE if Fn is None else counts.CLOVER_FLOPS_PER_SITE) * V / d_s / 1e9,
             "host_triad_gbs": triad,
         },
     }
@@ -387,20 +404,27 @@ def main():
     ctx = L.wilson_context_create()
     gbits = L.WILSON_GAUGE_FP32 | (L.WILSON_GAUGE_FP16 if precision == 2 else 0)
     g = L.wilson_gauge_load(ctx, U, dims, gbits)
+    clover = args.workload in CLOVER
+    F = None
+    if clover:
+        F = inputs.clover_field(dims, c=0.05, seed=1005, device=dev)
+        L.check(L.wilson_gauge_attach_clover(ctx, g, F, dims), "attach clover")
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     opts = {"precision": precision, "maxiter": 20000}
 
-    # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload) ----
+    # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload);
+    # for the clover matrix the hops of D_clov on both parities (T x - kappa H x) ----
     dprec = precision  # the workload's inner precision
+    dpar = 2 if clover else 0
     psi = srcs[0]  # all right-hand sides of the workload in one launch
     out = torch.zeros_like(psi)
     for _ in range(3):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec, nrhs), "dslash")
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, dpar, dprec, nrhs), "dslash")
     torch.cuda.synchronize()
     L.wilson_timing_enable(ctx, True)
     for _ in range(args.dslash_reps):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, dprec, nrhs), "dslash")
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, dpar, dprec, nrhs), "dslash")
     torch.cuda.synchronize()
     d_ms, d_n, d_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
     L.wilson_timing_enable(ctx, False)
@@ -414,20 +438,28 @@ def main():
         "us_per_launch": d_us,
         "launches": d_n,
         "algorithmic_bytes_per_launch": d_bytes / max(d_n, 1),
-        "bytes_per_site": 8 * counts.link_bytes(lname) + nrhs * 2 * counts.spinor_site_bytes(sname),
+        "bytes_per_site": d_bytes / max(d_n, 1) / Vh,
         "gbs": d_gbs,
         "frac_hbm_peak": d_gbs / counts.MI355X_HBM_GBS,
-        "gflops": counts.HOP_FLOPS_PER_SITE * Vh * nrhs / (d_us * 1e-6) / 1e9,
+        "gflops": (counts.CLOVER_FLOPS_PER_SITE if clover else counts.HOP_FLOPS_PER_SITE) * Vh * nrhs
+                  / (d_us * 1e-6) / 1e9,
         "working_set_mb": d_bytes / max(d_n, 1) / 1e6,
     }
+    if clover:  # both hops of one D_clov application, with the paper's ideal byte count
+        per_app = 1e-6 * d_us * 2
+        dslash["d_clov"] = {
+            "us_per_application": 2 * d_us,
+            "gflops_1944": counts.CLOVER_FLOPS_PER_SITE * V * nrhs / per_app / 1e9,
+            "gbs_ideal_count": counts.clover_full_bytes_per_site(lname if lname != "fp16" else "fp32") * V / per_app / 1e9,
+        }
 
     # ---- full D = 1 - kappa H on both parities (two hops, identity term fused); left out
     # of --dslash-only runs, whose hop launches are then all plain parity hops ----
     full_d = None
-    for _ in range(0 if args.dslash_only else 2):
+    for _ in range(0 if (args.dslash_only or clover) else 2):
         L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
     torch.cuda.synchronize()
-    if not args.dslash_only:
+    if not args.dslash_only and not clover:
         L.wilson_timing_enable(ctx, True)
         reps_d = max(args.dslash_reps // 2, 1)
         for _ in range(reps_d):
@@ -506,7 +538,8 @@ def main():
     traffic = committed_traffic(args.workload, dslash)
     roofline = {
         "bound": "hbm",
-        "kernel": f"parity hop (Dslash D_eo = -kappa H_eo), {sname} spinors, {nrhs} RHS, {list(dims)}",
+        "kernel": (f"parity hop of D_clov (T x - kappa H x), {sname} spinors, {list(dims)}" if clover else
+                   f"parity hop (Dslash D_eo = -kappa H_eo), {sname} spinors, {nrhs} RHS, {list(dims)}"),
         "achieved": d_gbs,
         "peak": counts.MI355X_HBM_GBS,
         "unit": "GB/s",
@@ -567,7 +600,7 @@ def main():
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)))
+        cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)), F)
 
     line = {
         "metric": METRIC,

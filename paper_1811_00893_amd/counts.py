@@ -19,6 +19,10 @@ neighbour spinors, the site spinor and the output.
 HOP_FLOPS_PER_SITE = 8 * (12 + 2 * 66) + 7 * 24  # 1320
 DIAG_FLOPS_PER_SITE = 48
 FULL_D_FLOPS_PER_SITE = HOP_FLOPS_PER_SITE + DIAG_FLOPS_PER_SITE  # 1368
+# clover matrix (Sec. 2.1.2): two Hermitian 6x6 block mat-vecs, each 36 complex products
+# (6 flop) and 30 complex additions (2 flop), on top of the Wilson count
+CLOVER_TERM_FLOPS_PER_SITE = 2 * (36 * 6 + 30 * 2)  # 552
+CLOVER_FLOPS_PER_SITE = FULL_D_FLOPS_PER_SITE + CLOVER_TERM_FLOPS_PER_SITE + 24  # 1944 (Table 1)
 
 REAL_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 
@@ -36,6 +40,16 @@ def hop_bytes_per_site(spinor_prec, link_prec=None):
     """Algorithmic bytes of the parity hop per output site."""
     link_prec = link_prec or spinor_prec
     return 8 * link_bytes(link_prec) + 2 * spinor_site_bytes(spinor_prec)
+
+
+def clover_term_bytes(prec):
+    """F(x) per site: two Hermitian 6x6 blocks = 72 reals."""
+    return 72 * REAL_BYTES[prec]
+
+
+def clover_full_bytes_per_site(prec):
+    """Algorithmic bytes of D_clov per site with ideal reuse: the Wilson count plus F."""
+    return full_d_bytes_per_site(prec) + clover_term_bytes(prec)
 
 
 def full_d_bytes_per_site(prec):

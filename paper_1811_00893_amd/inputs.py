@@ -90,11 +90,15 @@ def clover_field(dims, c=0.05, seed=1201, device="cpu"):
     Hermitian blocks in the chiral basis.  c = 0.05 keeps |F| near 0.25."""
     V = volume(dims)
     M = _gaussian_complex((V, 2, 12, 12), seed, device)
-    G = 0.5 * (M + M.conj().transpose(-1, -2))
-    g5 = torch.from_numpy(np.kron(_gamma5_dirac(), np.eye(3))).to(G.device, torch.complex128)
-    eye = torch.eye(12, dtype=torch.complex128, device=G.device)
+    g5 = torch.from_numpy(np.kron(_gamma5_dirac(), np.eye(3))).to(M.device, torch.complex128)
+    eye = torch.eye(12, dtype=torch.complex128, device=M.device)
     Pp, Pm = 0.5 * (eye + g5), 0.5 * (eye - g5)
-    F = c * (Pp @ G[:, 0] @ Pp + Pm @ G[:, 1] @ Pm)
+    F = torch.empty((V, 12, 12), dtype=torch.complex128, device=M.device)
+    chunk = 1 << 18
+    for i in range(0, V, chunk):
+        G = 0.5 * (M[i:i + chunk] + M[i:i + chunk].conj().transpose(-1, -2))
+        F[i:i + chunk] = c * (Pp @ G[:, 0] @ Pp + Pm @ G[:, 1] @ Pm)
+    del M
     return F
 
 

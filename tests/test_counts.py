@@ -40,6 +40,15 @@ def test_bytes_per_site_and_rooflines():
     assert abs(ofp / (ideal / 1368) - w["roofline_ofp_ideal"]) < 5
 
 
+def test_clover_counts():
+    c = GOLD["clover"]
+    assert counts.CLOVER_FLOPS_PER_SITE == c["flop_per_site"]
+    assert counts.table1_no_reuse_bytes_per_site("fp32") + counts.clover_term_bytes("fp32") == c["bytes_per_site_float"]
+    ideal = counts.clover_full_bytes_per_site("fp32")
+    assert round(ideal / counts.CLOVER_FLOPS_PER_SITE, 3) == c["byte_per_flop_ideal"]
+    assert counts.clover_full_bytes_per_site("fp64") == 1536
+
+
 def test_hop_bytes():
     assert counts.hop_bytes_per_site("fp64") == 1536
     assert counts.hop_bytes_per_site("fp32") == 768
