@@ -125,7 +125,7 @@ class Scheduler:
         while self.waiting:
             req = self.waiting.popleft()
             b = self._batch_for(req.gauge_id)
-            if b is not None:
+            if b is not None and not b.get("inflight"):  # slots change only between turns
                 for k, slot in enumerate(b["slots"]):
                     if not req.pending:
                         break
@@ -138,12 +138,35 @@ class Scheduler:
                 still.append(req)
         self.waiting = still
 
+    def _iters_for(self, b):
+        """Iterations of one batch per turn.  With a target turn length and an engine that
+        can estimate the cost of an iteration, each batch gets its own count, so a batch
+        on a small lattice advances many iterations while one on a large lattice does one
+        or two; otherwise the shared adaptive count."""
+        est = getattr(self.engine, "iter_ms", None)
+        if self.turn_ms and est is not None:
+            n = sum(s is not None for s in b["slots"])
+            ms = est(b["handle"], n)
+            return int(min(self.step_iters, max(1, round(self.turn_ms / max(ms, 1e-3)))))
+        return self.iters
+
     def step(self):
+        """One pass of the loop: start a turn on every batch with running slots that has
+        none in flight, then retire the slots of every batch whose turn has finished.  With
+        an engine that can tell whether a batch's turn is done (`ready`) the batches run
+        their turns independently (a small lattice does not wait for a large one's turn);
+        otherwise every started turn is waited for in this pass."""
         active = [b for b in self.batches.values() if any(s is not None for s in b["slots"])]
         t0 = time.perf_counter()
-        for b in active:                       # enqueue on every stream first ...
-            self.engine.step(b["handle"], self.iters)
-        for b in active:                       # ... then wait on each
+        ready = getattr(self.engine, "ready", None)
+        for b in active:                       # enqueue on every idle stream first ...
+            if not b.get("inflight"):
+                self.engine.step(b["handle"], self._iters_for(b))
+                b["inflight"] = True
+        for b in active:                       # ... then retire what has finished
+            if ready is not None and not ready(b["handle"]):
+                continue
+            b["inflight"] = False
             state, status = self.engine.poll(b["handle"])
             for k, slot in enumerate(b["slots"]):
                 if slot is None or state[k] != FINISHED:
@@ -159,7 +182,7 @@ class Scheduler:
                     self.engine.finish(req)
                     req.finish = self.clock()
                     self.completed.append(req)
-        if self.turn_ms and active:
+        if self.turn_ms and active and ready is None:
             # A slot whose Krylov cycle ends inside a turn waits for the turn to end before
             # its next cycle starts, so turns are kept short: a few milliseconds of work,
             # which on large lattices means polling every iteration or two.
@@ -168,7 +191,8 @@ class Scheduler:
             self.iters = int(min(self.step_iters, max(1, round(self.iters * min(max(scale, 0.5), 2.0)))))
 
     def busy(self):
-        return bool(self.waiting) or any(any(s is not None for s in b["slots"]) for b in self.batches.values())
+        return bool(self.waiting) or any(any(s is not None for s in b["slots"]) or b.get("inflight")
+                                         for b in self.batches.values())
 
     def run_until_idle(self, max_turns=10 ** 7):
         for _ in range(max_turns):
@@ -210,6 +234,18 @@ class LibEngine:
     def batch_bytes(self, dims, nslots):
         return self.L.wilson_footprint_bytes(dims, nslots, self.opts)
 
+    # Cost model of one batched iteration (milliseconds): a launch-bound floor (about a
+    # dozen kernels) plus the streamed bytes at a sustained rate: per right-hand side the
+    # four hops' spinor traffic and the vector updates (~2300 B per even site in FP32),
+    # and the links of the four hops, shared (~1536 B per even site).
+    LAUNCH_MS = 0.15
+    SUSTAINED_BYTES_PER_MS = 5.0e9
+
+    def iter_ms(self, handle, n_active):
+        dims = self.gauge[handle[0]][2]
+        vh = (dims[0] * dims[1] * dims[2] * dims[3]) // 2
+        return self.LAUNCH_MS + vh * (2300.0 * max(n_active, 1) + 1536.0) / self.SUSTAINED_BYTES_PER_MS
+
     def create_batch(self, gauge_id, nslots):
         ctx, g, dims, stream = self.gauge[gauge_id]
         return (gauge_id, self.L.wilson_batch_create(ctx, g, nslots, self.opts), nslots)
@@ -229,6 +265,10 @@ class LibEngine:
 
     def step(self, handle, iters):
         self.L.wilson_batch_step(handle[1], iters)
+
+    def ready(self, handle):
+        """True when the batch's stream has no work left (non-blocking)."""
+        return self.gauge[handle[0]][3].query()
 
     def poll(self, handle):
         return self.L.wilson_batch_poll(handle[1], handle[2])

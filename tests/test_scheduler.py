@@ -173,3 +173,58 @@ def test_turn_length_adapts_to_target():
     assert sch.iters == 16                     # short turns: back to the maximum
     sch.run_until_idle()
     assert len(sch.completed) == 1
+
+
+def test_per_batch_turn_length_from_engine_cost():
+    """An engine that estimates the cost of an iteration gets per-batch iteration counts:
+    the cheap batch advances many iterations per turn, the expensive one a few."""
+    class CostEngine(FakeEngine):
+        cost = {"small": 0.1, "big": 4.0}
+
+        def iter_ms(self, h, n_active):
+            return self.cost[h[0]]
+
+    eng = CostEngine()
+    sch = Scheduler(eng, hbm_budget=1e9, nslots=2, step_iters=32, clock=Clock(), turn_ms=4.0)
+    for gid in ("small", "big"):
+        sch.register_gauge(gid, (4, 4, 4, 4), 1)
+        sch.submit(mkreq(len(sch.waiting), gid, 1, kappa=0.5))
+    sch.admit()
+    assert sch._iters_for(sch.batches["small"]) == 32   # 4 ms / 0.1 ms, capped
+    assert sch._iters_for(sch.batches["big"]) == 1
+    sch.run_until_idle()
+    assert len(sch.completed) == 2
+
+
+def test_independent_turns_with_ready():
+    """With `ready`, a batch whose turn is still running is neither waited for nor given
+    new slots; other batches keep turning and completing."""
+    class AsyncEngine(FakeEngine):
+        def __init__(self):
+            super().__init__()
+            self.busy_polls = {}
+
+        def ready(self, h):
+            # the "slow" batch reports its turn done only every third query
+            if h[0] != "slow":
+                return True
+            self.busy_polls[h] = self.busy_polls.get(h, 0) + 1
+            return self.busy_polls[h] % 3 == 0
+
+    eng = AsyncEngine()
+    sch = Scheduler(eng, hbm_budget=1e9, nslots=2, step_iters=5, clock=Clock())
+    for gid in ("slow", "fast"):
+        sch.register_gauge(gid, (4, 4, 4, 4), 1)
+    sch.submit(mkreq(0, "slow", 2, kappa=0.05))
+    sch.submit(mkreq(1, "fast", 2, kappa=0.05))
+    sch.submit(mkreq(2, "slow", 1, kappa=0.05))  # waits for a free slot of the slow batch
+    steps_before = eng.steps
+    sch.admit()
+    sch.step()
+    assert sch.batches["slow"]["inflight"] and not sch.batches["fast"]["inflight"]
+    sch.admit()  # no attach into a batch with a turn in flight
+    assert [s[0].rid for s in sch.batches["slow"]["slots"]] == [0, 0]
+    sch.run_until_idle()
+    assert sorted(r.rid for r in sch.completed) == [0, 1, 2]
+    assert all(not b.get("inflight") for b in sch.batches.values())
+    assert eng.steps > steps_before
