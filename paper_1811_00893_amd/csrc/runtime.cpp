@@ -294,16 +294,24 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
                                       &c.shx) >= 4;
         }
     }
-    TuneTable &T = tune_table();
-    const std::string key = hop_key(a);
     LaunchCfg cfg;
-    {
+    const wilson_ctx::HotKey hk = {a.in.prec, a.gprec, a.recon, rhs_class(a.nrhs), {a.g.L[0], a.g.L[1], a.g.L[2], a.g.L[3]}};
+    const wilson_ctx::HotKey *found = nullptr;
+    for (const auto &e : ctx->hot)
+        if (e.first == hk) {
+            cfg = e.second;
+            found = &e.first;
+            break;
+        }
+    if (!found) {
+        TuneTable &T = tune_table();
+        const std::string key = hop_key(a);
         std::lock_guard<std::mutex> lk(T.mu);
         auto it = T.cfg.find(key);
         if (ctx->forced) {
-            cfg = fit_cfg(a, ctx->forced_cfg);  // keep the pinned order and block, fit the RHS split
+            cfg = ctx->forced_cfg;  // the pinned shape; fitted to each launch below
         } else if (it != T.cfg.end()) {
-            cfg = fit_cfg(a, it->second);
+            cfg = it->second;
         } else if (T.enabled && a.g.Vh >= 4096) {
             double ms = 0;
             cfg = tune_hop(ctx, a, &ms);
@@ -313,8 +321,11 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
             cfg = default_cfg(a);
             T.cfg[key] = cfg;
         }
+        if (ctx->hot.size() < 32) ctx->hot.push_back({hk, cfg});
     }
-    cfg = fit_cfg(a, cfg);  // a shape stored for the key may not suit this launch (clover, RHS count)
+    // a stored or pinned shape may not suit this launch (clover epilogue, RHS count): keep
+    // its order and block, fit the RHS split
+    cfg = fit_cfg(a, cfg);
     ctx->hop_launch_count++;
     if (ctx->timing) {
         hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();

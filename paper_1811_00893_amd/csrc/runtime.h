@@ -136,6 +136,16 @@ struct wilson_ctx {
     bool cfg_read = false;
     bool forced = false;
     wl::LaunchCfg forced_cfg;
+    // configurations already looked up by this context, keyed by launch shape (no string
+    // building and no lock on the per-launch path)
+    struct HotKey {
+        int sp, gp, rc, rhs, L[4];
+        bool operator==(const HotKey &o) const {
+            return sp == o.sp && gp == o.gp && rc == o.rc && rhs == o.rhs && L[0] == o.L[0] && L[1] == o.L[1] &&
+                   L[2] == o.L[2] && L[3] == o.L[3];
+        }
+    };
+    std::vector<std::pair<HotKey, wl::LaunchCfg>> hot;
     double t_ms[WILSON_KERNEL_COUNT] = {0, 0};
     int64_t launches[WILSON_KERNEL_COUNT] = {0, 0};
     double t_bytes[WILSON_KERNEL_COUNT] = {0, 0};
