@@ -11,7 +11,7 @@ over the timed region) against the MI355X HBM peak, a Dslash-only figure (parity
 alone), and the CPU oracle timed on a bounded sample of the same workload.
 
 Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | mixed48_fp16h |
-batched24 | clover32 | clover32_mixed | serve.
+batched24 | batched24_fp16 | clover32 | clover32_mixed | serve.
 """
 import argparse
 import json
@@ -88,6 +88,9 @@ WORKLOADS = {
                       "mixed precision (FP16 spinors + per-site scale, FP16 links inner; FP64 outer), 48^3x96"),
     "batched24": ((24, 24, 24, 48), 0.125, 1e-10, 1, 12,
                   "12 point sources in one batched solve, FP32 inner / FP64 outer, 24^3x48, kappa=0.125"),
+    "batched24_fp16": ((24, 24, 24, 48), 0.125, 1e-10, 3, 12,
+                       "12 point sources in one batched solve, FP16 spinors + per-site scale and FP32 links "
+                       "inner / FP64 outer, 24^3x48, kappa=0.125"),
     "clover32": ((32, 32, 32, 64), 0.125, 1e-10, 0, 1,
                  "clover matrix D_W + F, plain FP64 even-odd BiCGStab, 32^3x64, kappa=0.125, synthetic F (c=0.05)"),
     "clover32_mixed": ((32, 32, 32, 64), 0.125, 1e-10, 1, 1,

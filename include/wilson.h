@@ -171,7 +171,8 @@ size_t wilson_gauge_bytes(const wilson_gauge *g);
  *      library's Dirac basis (gamma5 = -[[0,1],[1,0]] on the spin pairs (0,2), (1,3));
  *      host or device; read during the call only.
  * The library keeps T and T^-1 per site as packed chiral blocks in FP64 and FP32
- * (1728 bytes per site).  Attaching again replaces the term.
+ * (1728 bytes per site).  Attaching again replaces the term.  The term must not change
+ * (attach or detach) while a batch on g has busy slots or a call on g is in progress.
  * Errors: INVALID_ARG (NULL; F not Hermitian or not commuting with gamma5 beyond a
  * relative 1e-12; T singular at some site), OUT_OF_MEMORY, DEVICE_ERROR; on error the
  * field keeps its previous state.
