@@ -21,14 +21,140 @@
 
 namespace wl {
 
-constexpr int kBlasBlock = 256;
+// Operands of the ops (BlasOp in common.h), by slot: which are read and which written.
+enum : int { SA = 1, SB = 2, SC = 4, SD = 8, SE = 16, SX = 32 };
+template <int OP>
+struct OpShape;
+template <> struct OpShape<BL_P_UPDATE> { static constexpr int LD = SA | SB | SC, ST = SA, NV = 0; };
+template <> struct OpShape<BL_S_UPDATE> { static constexpr int LD = SB | SC, ST = SA, NV = 1; };
+template <> struct OpShape<BL_XR_UPDATE> { static constexpr int LD = SA | SB | SD | SE | SX, ST = SC | SX, NV = 3; };
+template <> struct OpShape<BL_COPY_NORM> { static constexpr int LD = SB, ST = SA, NV = 1; };
+template <> struct OpShape<BL_CG_XR> { static constexpr int LD = SA | SB | SC | SX, ST = SB | SX, NV = 1; };
+template <> struct OpShape<BL_CG_P> { static constexpr int LD = SA | SB, ST = SA, NV = 0; };
+template <> struct OpShape<BL_NORM2> { static constexpr int LD = SA, ST = 0, NV = 1; };
 
-int blas_nblocks(const Geom &g) { return (g.Vh + kBlasBlock - 1) / kBlasBlock; }
+// N complex numbers of every operand slot (a whole site, or one 16-byte element).
+template <int N, typename R, typename RX>
+struct Opnds {
+    Cx<R> a[N], b[N], c[N], d[N], e[N];
+    Cx<RX> x[N];
+};
+
+template <typename R>
+__device__ __forceinline__ double norm2_of(Cx<R> v) {
+    return (double)v.re * v.re + (double)v.im * v.im;
+}
+
+// The arithmetic of one op on N complex numbers; reductions accumulate into red (FP64).
+template <int OP, int N, typename R, typename RX>
+__device__ __forceinline__ void blas_math(const RhsState *st, Opnds<N, R, RX> &o, double (&red)[3]) {
+    if constexpr (OP == BL_P_UPDATE) {
+        const Cx<R> beta = {(R)st->beta_re, (R)st->beta_im};
+        const Cx<R> omega = {(R)st->omega_re, (R)st->omega_im};
+#pragma unroll
+        for (int k = 0; k < N; k++) o.a[k] = cadd(o.b[k], cmul(beta, csub(o.a[k], cmul(omega, o.c[k]))));
+    } else if constexpr (OP == BL_S_UPDATE) {
+        const Cx<R> alpha = {(R)st->alpha_re, (R)st->alpha_im};
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            o.a[k] = csub(o.b[k], cmul(alpha, o.c[k]));
+            red[0] += norm2_of(o.a[k]);
+        }
+    } else if constexpr (OP == BL_XR_UPDATE) {
+        const Cx<RX> alpha = {(RX)st->alpha_re, (RX)st->alpha_im};
+        const Cx<RX> omega_x = {(RX)st->omega_re, (RX)st->omega_im};
+        const Cx<R> omega = {(R)st->omega_re, (R)st->omega_im};
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            const Cx<RX> pk = {(RX)o.a[k].re, (RX)o.a[k].im}, sk = {(RX)o.b[k].re, (RX)o.b[k].im};
+            o.x[k] = cadd(o.x[k], cadd(cmul(alpha, pk), cmul(omega_x, sk)));
+            const Cx<R> r = csub(o.b[k], cmul(omega, o.d[k]));
+            o.c[k] = r;
+            red[0] += norm2_of(r);
+            red[1] += (double)o.e[k].re * r.re + (double)o.e[k].im * r.im;  // <rhat, r>
+            red[2] += (double)o.e[k].re * r.im - (double)o.e[k].im * r.re;
+        }
+    } else if constexpr (OP == BL_COPY_NORM) {
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            o.a[k] = o.b[k];
+            red[0] += norm2_of(o.b[k]);
+        }
+    } else if constexpr (OP == BL_CG_XR) {
+        const RX alpha_x = (RX)st->alpha_re;
+        const R alpha = (R)st->alpha_re;
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            o.x[k] = cadd(o.x[k], cscale(Cx<RX>{(RX)o.a[k].re, (RX)o.a[k].im}, alpha_x));
+            o.b[k] = csub(o.b[k], cscale(o.c[k], alpha));
+            red[0] += norm2_of(o.b[k]);
+        }
+    } else if constexpr (OP == BL_CG_P) {
+        const R beta = (R)st->beta_re;
+#pragma unroll
+        for (int k = 0; k < N; k++) o.a[k] = cadd(o.b[k], cscale(o.a[k], beta));
+    } else if constexpr (OP == BL_NORM2) {
+#pragma unroll
+        for (int k = 0; k < N; k++) red[0] += norm2_of(o.a[k]);
+    }
+}
+
+// FP64 and FP32 storage: one 16-byte element (1 or 2 complex numbers) of one site per
+// thread.  Every op is elementwise over the spinor components, so a thread holds one
+// element of each operand: few registers, many waves in flight, and each wave reads and
+// writes whole contiguous runs of one plane.  A block covers kElemBlock consecutive sites
+// of one element plane (blockIdx.x = plane * nbs + site block) and leaves one partial per
+// reduced value.
+constexpr int kElemBlock = 1024;
+
+template <int P, int OP>
+__global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a, int nbs) {
+    using R = real_t<P>;
+    using S = OpShape<OP>;
+    constexpr int CPE = SpinorPack<P>::CPE, NEL = SpinorPack<P>::NEL;
+    const int rhs = blockIdx.y;
+    const RhsState *st = a.state ? &a.state[rhs] : nullptr;
+    if (st && !(st->phase & a.run_mask)) return;
+    const int e = blockIdx.x / nbs;
+    const int i_raw = (blockIdx.x - e * nbs) * kElemBlock + threadIdx.x;
+    const bool valid = i_raw < a.g.Vh;
+    const unsigned off = (unsigned)(valid ? i_raw : a.g.Vh - 1) * 16u;
+    const int plane = rhs * NEL + e, stride = a.g.stride;
+    Opnds<CPE, R, R> o;
+    if constexpr (S::LD & SA) ld_elem<P, R>(o.a, splane(a.a.data, plane, stride), off);
+    if constexpr (S::LD & SB) ld_elem<P, R>(o.b, splane(a.b.data, plane, stride), off);
+    if constexpr (S::LD & SC) ld_elem<P, R>(o.c, splane(a.c.data, plane, stride), off);
+    if constexpr (S::LD & SD) ld_elem<P, R>(o.d, splane(a.d.data, plane, stride), off);
+    if constexpr (S::LD & SE) ld_elem<P, R>(o.e, splane(a.e.data, plane, stride), off);
+    if constexpr (S::LD & SX) ld_elem<P, R>(o.x, splane(a.x.data, plane, stride), off);
+    double red[3] = {0.0, 0.0, 0.0};
+    blas_math<OP, CPE, R, R>(st, o, red);
+    if (valid) {
+        if constexpr (S::ST & SA) st_elem<P, R>(const_cast<char *>(splane(a.a.data, plane, stride)), off, o.a);
+        if constexpr (S::ST & SB) st_elem<P, R>(const_cast<char *>(splane(a.b.data, plane, stride)), off, o.b);
+        if constexpr (S::ST & SC) st_elem<P, R>(const_cast<char *>(splane(a.c.data, plane, stride)), off, o.c);
+        if constexpr (S::ST & SX) st_elem<P, R>(const_cast<char *>(splane(a.x.data, plane, stride)), off, o.x);
+    } else {
+        red[0] = red[1] = red[2] = 0.0;
+    }
+    if constexpr (S::NV > 0) {
+        const int ps = a.pstride ? a.pstride : (int)gridDim.x;
+        double v[S::NV];
+#pragma unroll
+        for (int k = 0; k < S::NV; k++) v[k] = red[k];
+        block_reduce_to<S::NV>(v, a.partials + (size_t)rhs * S::NV * ps + blockIdx.x, ps);
+    }
+}
+
+// FP16 storage: the per-site scale couples all 24 reals of a site, so one thread takes a
+// whole site (x may be FP32 or FP16).
+constexpr int kSiteBlock = 256;
 
 template <int PK, int PX, int OP>
-__global__ void __launch_bounds__(kBlasBlock) blas_kernel(const BlasArgs a) {
+__global__ void __launch_bounds__(kSiteBlock) blas_site_kernel(const BlasArgs a) {
     using R = real_t<PK>;
     using RX = real_t<PX>;
+    using S = OpShape<OP>;
     const int rhs = blockIdx.y;
     const RhsState *st = a.state ? &a.state[rhs] : nullptr;
     if (st && !(st->phase & a.run_mask)) return;
@@ -36,139 +162,71 @@ __global__ void __launch_bounds__(kBlasBlock) blas_kernel(const BlasArgs a) {
     const int i_raw = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i_raw < a.g.Vh;
     const int i = valid ? i_raw : a.g.Vh - 1;
-    double *dst = a.partials;
-    const int ps = a.pstride ? a.pstride : (int)gridDim.x;
-
-    if constexpr (OP == BL_P_UPDATE) {
-        const Cx<R> beta = {(R)st->beta_re, (R)st->beta_im};
-        const Cx<R> omega = {(R)st->omega_re, (R)st->omega_im};
-        Cx<R> p[12], r[12], v[12];
-        load_site<PK, R>(p, a.a, stride, rhs, i);
-        load_site<PK, R>(r, a.b, stride, rhs, i);
-        load_site<PK, R>(v, a.c, stride, rhs, i);
+    Opnds<12, R, RX> o;
+    if constexpr (S::LD & SA) load_site<PK, R>(o.a, a.a, stride, rhs, i);
+    if constexpr (S::LD & SB) load_site<PK, R>(o.b, a.b, stride, rhs, i);
+    if constexpr (S::LD & SC) load_site<PK, R>(o.c, a.c, stride, rhs, i);
+    if constexpr (S::LD & SD) load_site<PK, R>(o.d, a.d, stride, rhs, i);
+    if constexpr (S::LD & SE) load_site<PK, R>(o.e, a.e, stride, rhs, i);
+    if constexpr (S::LD & SX) load_site<PX, RX>(o.x, a.x, stride, rhs, i);
+    double red[3] = {0.0, 0.0, 0.0};
+    blas_math<OP, 12, R, RX>(st, o, red);
+    if (valid) {
+        if constexpr (S::ST & SA) store_site<PK, R>(a.a, stride, rhs, i, o.a);
+        if constexpr (S::ST & SB) store_site<PK, R>(a.b, stride, rhs, i, o.b);
+        if constexpr (S::ST & SC) store_site<PK, R>(a.c, stride, rhs, i, o.c);
+        if constexpr (S::ST & SX) store_site<PX, RX>(a.x, stride, rhs, i, o.x);
+    } else {
+        red[0] = red[1] = red[2] = 0.0;
+    }
+    if constexpr (S::NV > 0) {
+        const int ps = a.pstride ? a.pstride : (int)gridDim.x;
+        double v[S::NV];
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
-            Cx<R> q = csub(p[k], cmul(omega, v[k]));
-            p[k] = cadd(r[k], cmul(beta, q));
-        }
-        if (valid) store_site<PK, R>(a.a, stride, rhs, i, p);
-    } else if constexpr (OP == BL_S_UPDATE) {
-        const Cx<R> alpha = {(R)st->alpha_re, (R)st->alpha_im};
-        Cx<R> r[12], v[12], s[12];
-        load_site<PK, R>(r, a.b, stride, rhs, i);
-        load_site<PK, R>(v, a.c, stride, rhs, i);
-        double n2[1] = {0.0};
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            s[k] = csub(r[k], cmul(alpha, v[k]));
-            n2[0] += (double)s[k].re * s[k].re + (double)s[k].im * s[k].im;
-        }
-        if (valid) store_site<PK, R>(a.a, stride, rhs, i, s);
-        else n2[0] = 0.0;
-        block_reduce_to<1>(n2, dst + (size_t)rhs * ps + blockIdx.x, ps);
-    } else if constexpr (OP == BL_XR_UPDATE) {
-        const Cx<RX> alpha = {(RX)st->alpha_re, (RX)st->alpha_im};
-        const Cx<RX> omega_x = {(RX)st->omega_re, (RX)st->omega_im};
-        const Cx<R> omega = {(R)st->omega_re, (R)st->omega_im};
-        Cx<R> p[12], s[12], t[12], rh[12];
-        Cx<RX> x[12];
-        load_site<PK, R>(p, a.a, stride, rhs, i);
-        load_site<PK, R>(s, a.b, stride, rhs, i);
-        load_site<PK, R>(t, a.d, stride, rhs, i);
-        load_site<PK, R>(rh, a.e, stride, rhs, i);
-        load_site<PX, RX>(x, a.x, stride, rhs, i);
-        double red[3] = {0.0, 0.0, 0.0};
-        Cx<R> r[12];
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            const Cx<RX> pk = {(RX)p[k].re, (RX)p[k].im}, sk = {(RX)s[k].re, (RX)s[k].im};
-            x[k] = cadd(x[k], cadd(cmul(alpha, pk), cmul(omega_x, sk)));
-            r[k] = csub(s[k], cmul(omega, t[k]));
-            red[0] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
-            red[1] += (double)rh[k].re * r[k].re + (double)rh[k].im * r[k].im;  // <rhat, r>
-            red[2] += (double)rh[k].re * r[k].im - (double)rh[k].im * r[k].re;
-        }
-        if (valid) {
-            store_site<PX, RX>(a.x, stride, rhs, i, x);
-            store_site<PK, R>(a.c, stride, rhs, i, r);
-        } else {
-            red[0] = red[1] = red[2] = 0.0;
-        }
-        block_reduce_to<3>(red, dst + (size_t)rhs * 3 * ps + blockIdx.x, ps);
-    } else if constexpr (OP == BL_COPY_NORM) {
-        Cx<R> v[12];
-        load_site<PK, R>(v, a.b, stride, rhs, i);
-        double n2[1] = {0.0};
-#pragma unroll
-        for (int k = 0; k < 12; k++) n2[0] += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
-        if (valid) store_site<PK, R>(a.a, stride, rhs, i, v);
-        else n2[0] = 0.0;
-        block_reduce_to<1>(n2, dst + (size_t)rhs * ps + blockIdx.x, ps);
-    } else if constexpr (OP == BL_CG_XR) {
-        const RX alpha_x = (RX)st->alpha_re;
-        const R alpha = (R)st->alpha_re;
-        Cx<R> p[12], r[12], w[12];
-        Cx<RX> x[12];
-        load_site<PK, R>(p, a.a, stride, rhs, i);
-        load_site<PK, R>(r, a.b, stride, rhs, i);
-        load_site<PK, R>(w, a.c, stride, rhs, i);
-        load_site<PX, RX>(x, a.x, stride, rhs, i);
-        double n2[1] = {0.0};
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            x[k] = cadd(x[k], cscale(Cx<RX>{(RX)p[k].re, (RX)p[k].im}, alpha_x));
-            r[k] = csub(r[k], cscale(w[k], alpha));
-            n2[0] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
-        }
-        if (valid) {
-            store_site<PX, RX>(a.x, stride, rhs, i, x);
-            store_site<PK, R>(a.b, stride, rhs, i, r);
-        } else {
-            n2[0] = 0.0;
-        }
-        block_reduce_to<1>(n2, dst + (size_t)rhs * ps + blockIdx.x, ps);
-    } else if constexpr (OP == BL_CG_P) {
-        const R beta = (R)st->beta_re;
-        Cx<R> p[12], z[12];
-        load_site<PK, R>(p, a.a, stride, rhs, i);
-        load_site<PK, R>(z, a.b, stride, rhs, i);
-#pragma unroll
-        for (int k = 0; k < 12; k++) p[k] = cadd(z[k], cscale(p[k], beta));
-        if (valid) store_site<PK, R>(a.a, stride, rhs, i, p);
-    } else if constexpr (OP == BL_NORM2) {
-        Cx<R> v[12];
-        load_site<PK, R>(v, a.a, stride, rhs, i);
-        double n2[1] = {0.0};
-        if (valid)
-#pragma unroll
-            for (int k = 0; k < 12; k++) n2[0] += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
-        block_reduce_to<1>(n2, dst + (size_t)rhs * ps + blockIdx.x, ps);
+        for (int k = 0; k < S::NV; k++) v[k] = red[k];
+        block_reduce_to<S::NV>(v, a.partials + (size_t)rhs * S::NV * ps + blockIdx.x, ps);
     }
 }
 
-template <int PK, int PX>
-static hipError_t launch_blas_t(int op, const BlasArgs &a, hipStream_t s) {
-    dim3 grid(blas_nblocks(a.g), a.nrhs), block(kBlasBlock);
-    switch (op) {
-        case BL_P_UPDATE: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_P_UPDATE>), grid, block, 0, s, a); break;
-        case BL_S_UPDATE: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_S_UPDATE>), grid, block, 0, s, a); break;
-        case BL_XR_UPDATE: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_XR_UPDATE>), grid, block, 0, s, a); break;
-        case BL_COPY_NORM: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_COPY_NORM>), grid, block, 0, s, a); break;
-        case BL_CG_XR: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_CG_XR>), grid, block, 0, s, a); break;
-        case BL_CG_P: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_CG_P>), grid, block, 0, s, a); break;
-        case BL_NORM2: hipLaunchKernelGGL((blas_kernel<PK, PX, BL_NORM2>), grid, block, 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
+int blas_nblocks(const Geom &g, int prec) {
+    if (prec == P16) return (g.Vh + kSiteBlock - 1) / kSiteBlock;
+    return (prec == P64 ? 12 : 6) * ((g.Vh + kElemBlock - 1) / kElemBlock);
+}
+
+template <int OP>
+static void launch_op_elem(int pk, const BlasArgs &a, hipStream_t s) {
+    const int nbs = (a.g.Vh + kElemBlock - 1) / kElemBlock;
+    const dim3 grid(blas_nblocks(a.g, pk), a.nrhs), block(kElemBlock);
+    if (pk == P64) hipLaunchKernelGGL((blas_elem_kernel<P64, OP>), grid, block, 0, s, a, nbs);
+    else hipLaunchKernelGGL((blas_elem_kernel<P32, OP>), grid, block, 0, s, a, nbs);
+}
+template <int PX, int OP>
+static void launch_op_site(const BlasArgs &a, hipStream_t s) {
+    const dim3 grid(blas_nblocks(a.g, P16), a.nrhs), block(kSiteBlock);
+    hipLaunchKernelGGL((blas_site_kernel<P16, PX, OP>), grid, block, 0, s, a);
+}
+template <int OP>
+static hipError_t launch_op(int pk, int px, const BlasArgs &a, hipStream_t s) {
+    if ((pk == P64 || pk == P32) && px == pk) launch_op_elem<OP>(pk, a, s);
+    else if (pk == P16 && px == P32) launch_op_site<P32, OP>(a, s);
+    else if (pk == P16 && px == P16) launch_op_site<P16, OP>(a, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_blas(int op, const BlasArgs &a, hipStream_t s) {
     const int pk = a.a.prec, px = a.x.data ? a.x.prec : pk;
-    if (pk == P64 && px == P64) return launch_blas_t<P64, P64>(op, a, s);
-    if (pk == P32 && px == P32) return launch_blas_t<P32, P32>(op, a, s);
-    if (pk == P16 && px == P32) return launch_blas_t<P16, P32>(op, a, s);
-    if (pk == P16 && px == P16) return launch_blas_t<P16, P16>(op, a, s);
-    return hipErrorInvalidValue;
+    if (a.nrhs < 1 || a.nrhs > 65535) return hipErrorInvalidValue;
+    switch (op) {
+        case BL_P_UPDATE: return launch_op<BL_P_UPDATE>(pk, px, a, s);
+        case BL_S_UPDATE: return launch_op<BL_S_UPDATE>(pk, px, a, s);
+        case BL_XR_UPDATE: return launch_op<BL_XR_UPDATE>(pk, px, a, s);
+        case BL_COPY_NORM: return launch_op<BL_COPY_NORM>(pk, px, a, s);
+        case BL_CG_XR: return launch_op<BL_CG_XR>(pk, px, a, s);
+        case BL_CG_P: return launch_op<BL_CG_P>(pk, px, a, s);
+        case BL_NORM2: return launch_op<BL_NORM2>(pk, px, a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -182,7 +240,7 @@ __device__ void fin_op(RhsState *st, double a0, double a1, double a2);
 // mirror (optional, host-mapped): every RHS's state is copied there after the step, so
 // the host can poll convergence without a device-to-host copy on the stream.
 template <int OP>
-__global__ void __launch_bounds__(256) finalize_kernel(const double *partials, int nv, int nblocks,
+__global__ void __launch_bounds__(1024) finalize_kernel(const double *partials, int nv, int nblocks,
                                                        RhsState *state, int run_mask, RhsState *mirror) {
     const int rhs = blockIdx.x;
     RhsState *st = &state[rhs];
@@ -303,7 +361,9 @@ __device__ void fin_op(RhsState *st, const double a0, const double a1, const dou
 
 hipError_t launch_finalize(int op, const double *partials, int nvals, int nblocks, int nrhs, RhsState *state,
                            int run_mask, hipStream_t s, RhsState *mirror) {
-    dim3 grid(nrhs), block(256);
+    // a wider block keeps more loads in flight over long partial rows; the block size is a
+    // function of the row length alone, so the summation order stays fixed
+    dim3 grid(nrhs), block(nblocks > 4096 ? 1024 : 256);
 #define FIN_CASE(X) \
     case X: hipLaunchKernelGGL((finalize_kernel<X>), grid, block, 0, s, partials, nvals, nblocks, state, run_mask, mirror); break;
     switch (op) {

@@ -195,7 +195,8 @@ enum BlasOp : int {
     BL_CG_P,          // p(a) = z(b) + beta p
     BL_NORM2          // |a|^2
 };
-int blas_nblocks(const Geom &g);
+// partial sums one BLAS launch leaves per RHS and value (prec: storage precision of its operands)
+int blas_nblocks(const Geom &g, int prec);
 hipError_t launch_blas(int op, const BlasArgs &a, hipStream_t s);
 hipError_t launch_finalize(int op, const double *partials, int nvals, int nblocks, int nrhs, RhsState *state,
                            int run_mask, hipStream_t s, RhsState *mirror = nullptr);

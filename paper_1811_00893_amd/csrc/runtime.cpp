@@ -2,6 +2,7 @@
 // launch-configuration autotuner.
 #include "runtime.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -86,8 +87,10 @@ bool is_device_ptr(const void *p) {
 }
 
 size_t partials_doubles(const Geom &g, int nrhs) {
-    const size_t nb = (size_t)(g.Vh + 63) / 64;  // smallest block size the tuner uses
-    return (size_t)nrhs * 3 * nb * 2 + 64;       // x2: both parities in one row
+    const size_t hop_nb = (size_t)(g.Vh + 63) / 64 * 2;  // smallest hop tile; x2: both parities in one row
+    size_t nb = hop_nb;
+    for (int p : {P64, P32, P16}) nb = std::max(nb, (size_t)blas_nblocks(g, p));
+    return (size_t)nrhs * 3 * nb + 64;
 }
 
 double hop_bytes(const HopArgs &a) {

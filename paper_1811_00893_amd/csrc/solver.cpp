@@ -197,14 +197,13 @@ class EoCore {
 
     // |e|^2 + |o|^2 of FP64 fields into st[].aux
     void norm2_full(Spinor e, Spinor o, RhsState *st) {
-        const int nb = blas_nblocks(g);
         BlasArgs a = blas_args(nullptr, 0);
         a.a = e;
         run_blas(BL_NORM2, a, vec_bytes(e.prec, 1));
-        finalize(FIN_STORE_AUX, 1, nb, st, kAllPhases);
+        finalize(FIN_STORE_AUX, 1, blas_nblocks(g, e.prec), st, kAllPhases);
         a.a = o;
         run_blas(BL_NORM2, a, vec_bytes(o.prec, 1));
-        finalize(FIN_ADD_AUX, 1, nb, st, kAllPhases);
+        finalize(FIN_ADD_AUX, 1, blas_nblocks(g, o.prec), st, kAllPhases);
     }
 
     // host <-> device copies of the states of the selected range
@@ -281,7 +280,7 @@ class EoCore {
             h[k].stop2 = stop2[k];
         }
         upload_states(sin(), h);
-        const int nb = blas_nblocks(g);
+        const int nb = blas_nblocks(g, P);
         Spinor none;
         if (method == WILSON_SOLVER_BICGSTAB_EO) {
             // r = rhs - M x  (or rhs), rhat = r
@@ -346,7 +345,7 @@ class EoCore {
     }
 
     void bicg_iter(Spinor x, RhsState *mir) {
-        const int nb = blas_nblocks(g);
+        const int nb = blas_nblocks(g, P);
         Spinor none;
         {   // p = r + beta (p - omega v)
             BlasArgs a = blas_args(sin(), PH_RUN);
@@ -374,7 +373,7 @@ class EoCore {
     }
 
     void cg_iter(Spinor x, RhsState *mir) {
-        const int nb = blas_nblocks(g);
+        const int nb = blas_nblocks(g, P);
         Spinor none;
         // w = M p, |w|^2 -> alpha
         int hb = apply_M(v.f, p.f, tmp.f, false, RED_NORM2, none, sin(), PH_RUN);
@@ -711,7 +710,7 @@ class BatchEngine {
         h[0].phase = PH_RUN;
         h[0].stop2 = stop2;
         C->upload_states(C->sin(), h);
-        const int nb = blas_nblocks(C->g);
+        const int nb = blas_nblocks(C->g, C->P);
         Spinor none;
         if (C->method == WILSON_SOLVER_BICGSTAB_EO) {
             BlasArgs a = C->blas_args(C->sin(), PH_RUN);
