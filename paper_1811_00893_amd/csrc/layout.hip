@@ -147,42 +147,26 @@ __global__ void su3_check_kernel(const double2 *canon, size_t nlinks, double tol
     if (bad) atomicOr(flag, 1);
 }
 
-// Streaming copy: each thread moves 4 x 16 bytes per step (4 loads in flight before the
-// stores), grid-strided over the buffer.
+// Bandwidth probes.  One 16-byte element per thread and no loop: a wave moves one
+// contiguous 1 KiB run and ends, which keeps the most requests in flight on gfx950 (a
+// thread that loops waits for its own earlier stores before its next loads return).
 __global__ void __launch_bounds__(256) stream_copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
                                                           size_t n16) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    for (; k + 3 * stride < n16; k += 4 * stride) {
-        const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
-        dst[k] = a;
-        dst[k + stride] = b;
-        dst[k + 2 * stride] = c;
-        dst[k + 3 * stride] = d;
-    }
-    for (; k < n16; k += stride) dst[k] = src[k];
+    const size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (k < n16) dst[k] = src[k];
 }
 
-// Read-only stream: sums the buffer as 32-bit words (4 x 16-byte loads in flight per
-// thread) and writes one word per block so the loads cannot be elided.
+// Read-only stream: each lane folds its 16 bytes into one word and, only when that word
+// equals an arbitrary constant, XORs it into one of kStreamSink words.  The branch depends
+// on the data, so no load can be elided, and almost no lane ever writes.
+constexpr unsigned kStreamSink = 8192;
 __global__ void __launch_bounds__(256) stream_read_kernel(const uint4 *__restrict__ src, size_t n16,
                                                           unsigned *sink) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    unsigned acc = 0;
-    for (; k + 3 * stride < n16; k += 4 * stride) {
-        const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
-        acc += a.x ^ b.y ^ c.z ^ d.w;
-        acc += a.w ^ b.x ^ c.y ^ d.z;
-    }
-    for (; k < n16; k += stride) acc += src[k].x;
-    __shared__ unsigned red[256];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = 0;
-        for (int j = 0; j < (int)blockDim.x; j++) t += red[j];
-        sink[blockIdx.x] = t;
+    const size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (k < n16) {
+        const uint4 a = src[k];
+        const unsigned w = a.x ^ a.y ^ a.z ^ a.w;
+        if (w == 0x9E3779B9u) atomicXor(&sink[k % kStreamSink], w);
     }
 }
 
@@ -200,7 +184,6 @@ __global__ void check_finite_kernel(const double *p, size_t n, int *flag) {
 
 // ---------------------------------------------------------------------------------
 static inline dim3 site_grid(const Geom &g, int ny) { return dim3((g.Vh + 255) / 256, ny); }
-constexpr unsigned kStreamBlocks = 8192;  // 32 blocks of 256 threads per CU
 
 hipError_t launch_to_parity(Spinor f, const double *canon, const Geom &g, int par, int nrhs, double scale,
                             hipStream_t s) {
@@ -273,17 +256,16 @@ hipError_t launch_su3_check(const double *canon, size_t nlinks, double tol, int 
 
 hipError_t launch_stream_read(const void *src, size_t bytes, unsigned *sink, hipStream_t s) {
     const size_t n16 = bytes / 16;
-    hipLaunchKernelGGL(stream_read_kernel, dim3(kStreamBlocks), dim3(256), 0, s, (const uint4 *)src, n16, sink);
+    if (n16) hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s,
+                                (const uint4 *)src, n16, sink);
     return hipGetLastError();
 }
 
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
     const size_t n16 = bytes / 16;
-    if (n16) {
-        const size_t want = (n16 + 255) / 256;
-        const unsigned blocks = (unsigned)(want < kStreamBlocks ? want : kStreamBlocks);
-        hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n16);
-    }
+    if (n16)
+        hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s, (uint4 *)dst,
+                           (const uint4 *)src, n16);
     const size_t tail = bytes - n16 * 16;
     if (tail)
         hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(64), 0, s, (unsigned char *)dst + n16 * 16,
