@@ -302,6 +302,84 @@ def run_serving(args):
     }
 
 
+def run_layouts(args):
+    """Layout ablation: the parity hop of one kernel under each storage layout (site-per-lane
+    planes, array of structures, 64-site tiles, sub-lattice lanes), FP64 and FP32, links
+    stored as 18 or 12 reals, on 32^3x64; the library's production hop is timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_1811_00893_amd import _lib as L
+    from paper_1811_00893_amd import counts, inputs
+
+    dims, kappa = (32, 32, 32, 64), 0.125
+    dev = torch.device("cuda:0")
+    Vh = int(np.prod(dims)) // 2
+    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=dev)
+    psi = inputs.gaussian_source(dims, seed=2002, device=dev)
+    out = torch.zeros_like(psi)
+    ctx = L.wilson_context_create()
+    reps = max(args.dslash_reps // 2, 5)
+    rows = []
+    t0 = time.perf_counter()
+    for prec, pname in ((0, "fp64"), (1, "fp32")):
+        rb = counts.REAL_BYTES[pname]
+        for link_reals in (18, 12):
+            for name, lay in (("soa", 0), ("aos", 1), ("aosoa", 2), ("vnode", 3)):
+                st, us = L.wilson_layout_hop(ctx, out, psi, U, dims, kappa, 0, prec, lay, link_reals, reps)
+                L.check(st, f"layout hop {name}")
+                alg = counts.hop_bytes_per_site(pname) * Vh
+                stored = (8 * link_reals + 48) * rb * Vh
+                rows.append({"layout": name, "precision": pname, "link_reals": link_reals, "us_per_launch": us,
+                             "gbs_algorithmic": alg / (us * 1e-6) / 1e9,
+                             "frac_hbm_peak": alg / (us * 1e-6) / 1e9 / counts.MI355X_HBM_GBS,
+                             "gbs_stored_bytes": stored / (us * 1e-6) / 1e9})
+                print(f"layout {name} {pname} links {link_reals}: {us:.1f} us", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    # the production kernel on the same fields (tuned launch, link storage chosen at upload)
+    g = L.wilson_gauge_load(ctx, U, dims, L.WILSON_GAUGE_FP32)
+    prod = {}
+    for prec, pname in ((0, "fp64"), (1, "fp32")):
+        for _ in range(3):
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, prec, 1), "dslash")
+        torch.cuda.synchronize()
+        L.wilson_timing_enable(ctx, True)
+        for _ in range(reps):
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 0, prec, 1), "dslash")
+        torch.cuda.synchronize()
+        ms, n, _ = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
+        L.wilson_timing_enable(ctx, False)
+        us = 1e3 * ms / max(n, 1)
+        alg = counts.hop_bytes_per_site(pname) * Vh
+        prod[pname] = {"us_per_launch": us, "gbs_algorithmic": alg / (us * 1e-6) / 1e9}
+    L.wilson_gauge_free(ctx, g)
+    # 2 GiB copy probe: bandwidth reference, and the calibration of hardware byte counters
+    nb = 1 << 31
+    src_buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    dst_buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        L.wilson_stream_copy(ctx, dst_buf, src_buf, nb)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        L.wilson_stream_copy(ctx, dst_buf, src_buf, nb)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * nb / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src_buf, dst_buf
+    L.wilson_context_destroy(ctx)
+    best = next(r for r in rows if r["layout"] == "soa" and r["precision"] == "fp64" and r["link_reals"] == 12)
+    return {
+        "metric": "parity-hop GB/s (algorithmic bytes) by storage layout",
+        "value": best["gbs_algorithmic"], "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": best["us_per_launch"] / 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
+        "config": {"workload": "layout ablation of the parity hop (value: site-per-lane planes, FP64, 12-real "
+                               "links), 32^3x64, kappa=0.125, eps=0.3", "dims": list(dims)},
+        "layouts": rows, "production_hop": prod, "hbm_copy_gbs": copy_gbs, "ablation_seconds": elapsed,
+    }
+
+
 def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None):
     """The FP64 oracle timed on the host: an even-odd BiCGStab solve (run for 1 and 1+k
     iterations, whose difference isolates the cost of an iteration, scaled to the number
@@ -384,6 +462,9 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         print(json.dumps(run_serving(args)), flush=True)
+        return
+    if args.workload == "layouts":
+        print(json.dumps(run_layouts(args)), flush=True)
         return
     import numpy as np
     import torch

@@ -251,6 +251,46 @@ int wilson_stream_copy(wilson_ctx *ctx, void *dst, const void *src, size_t bytes
  * (read-only bandwidth reference; the data is not modified). */
 int wilson_stream_read(wilson_ctx *ctx, const void *src, size_t bytes);
 
+/* ---------------------------------------------------------------------------------- */
+/* Layout ablation.                                                                    */
+/* ---------------------------------------------------------------------------------- */
+
+/* Storage layouts of wilson_layout_hop (Sec. 4.1 compares folding consecutive x-sites
+ * into one SIMD vector, its layout 1, with folding one site of each of several
+ * sub-lattices into it, its layout 2; Sec. 5 also compares both with the
+ * array-of-structures base code).  A GPU wavefront plays the vector. */
+typedef enum {
+    WILSON_LAYOUT_SOA = 0,    /* component planes over checkerboard sites: 64 consecutive
+                                 x-sites per wavefront (layout 1; the library's own) */
+    WILSON_LAYOUT_AOS = 1,    /* the 12 complex of a site contiguous, the 4 links of a site
+                                 contiguous (the base code's array of structures) */
+    WILSON_LAYOUT_AOSOA = 2,  /* tiles of 64 sites, component planes inside a tile */
+    WILSON_LAYOUT_VNODE = 3   /* 1 x 4 x 4 x 4 sub-lattices; lane l of a wavefront holds
+                                 sub-lattice l (layout 2); needs Ly, Lz, Lt multiples of 8 */
+} wilson_layout;
+
+/* The parity hop out = -kappa H_{p,1-p} in (Eq. (1); the same operation as
+ * wilson_dslash_ex with parity p), computed by one kernel whose spinor and link fields
+ * are stored in `layout`; everything but the addressing is shared by the layouts.
+ *   out, in   canonical complex128 fields of the whole lattice (12*V complex, layout of
+ *             wilson_dslash), device memory.  in is read on the sites of parity 1-parity;
+ *             out receives the hop on the sites of `parity` and zero on the others.
+ *   U         canonical complex128 links (4*V*9 complex), device memory.
+ *   parity    0 or 1.
+ *   precision WILSON_FP64 or WILSON_FP32: storage and arithmetic of fields and links.
+ *   link_reals 18 (full links) or 12 (first two rows; U must then be SU(3) to 1e-13).
+ *   reps      >= 0 further launches after the one whose result is returned, timed with
+ *             HIP events on the context stream; *us_per_launch (may be NULL) receives
+ *             their mean duration in microseconds (0 when reps == 0).
+ * The call packs the fields into the layout in device buffers of its own (freed before
+ * it returns; not part of the timing) and synchronizes the context stream.
+ * Errors: WILSON_INVALID_ARG (NULL or host pointer, extents not allowed for the layout,
+ * bad parity/precision/layout/link_reals/reps, U not SU(3) with link_reals 12),
+ * WILSON_OUT_OF_MEMORY, WILSON_DEVICE_ERROR. */
+int wilson_layout_hop(wilson_ctx *ctx, double *out, const double *in, const double *U, const int32_t dims[4],
+                      double kappa, int32_t parity, int32_t precision, int32_t layout, int32_t link_reals,
+                      int32_t reps, double *us_per_launch);
+
 const char *wilson_strerror(int code);
 const char *wilson_last_error(void);
 /* Library version string. */

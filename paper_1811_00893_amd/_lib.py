@@ -32,6 +32,7 @@ WILSON_FP64, WILSON_FP32, WILSON_FP16, WILSON_FP16_L32 = 0, 1, 2, 3
 WILSON_GAUGE_FP64, WILSON_GAUGE_FP32, WILSON_GAUGE_FP16 = 1, 2, 4
 WILSON_SOLVER_BICGSTAB_EO, WILSON_SOLVER_CGNR_EO = 0, 1
 WILSON_KERNEL_HOP, WILSON_KERNEL_BLAS = 0, 1
+WILSON_LAYOUT_SOA, WILSON_LAYOUT_AOS, WILSON_LAYOUT_AOSOA, WILSON_LAYOUT_VNODE = 0, 1, 2, 3
 
 EXPORTS = [
     "wilson_dslash", "wilson_solve", "wilson_context_create", "wilson_context_destroy", "wilson_gauge_load",
@@ -39,7 +40,7 @@ EXPORTS = [
     "wilson_batch_create", "wilson_batch_destroy", "wilson_batch_attach", "wilson_batch_step", "wilson_batch_poll",
     "wilson_batch_detach", "wilson_timing_enable", "wilson_timing_read", "wilson_stream_copy", "wilson_strerror",
     "wilson_last_error", "wilson_version", "wilson_stream_read", "wilson_gauge_attach_clover",
-    "wilson_gauge_detach_clover",
+    "wilson_gauge_detach_clover", "wilson_layout_hop",
 ]
 
 
@@ -86,6 +87,7 @@ _SIGS = {
                                   ctypes.POINTER(_d)]),
     "wilson_stream_copy": (_i32, [_vp, _vp, _vp, ctypes.c_size_t]),
     "wilson_stream_read": (_i32, [_vp, _vp, ctypes.c_size_t]),
+    "wilson_layout_hop": (_i32, [_vp, _vp, _vp, _vp, _vp, _d, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_d)]),
     "wilson_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "wilson_last_error": (ctypes.c_char_p, []),
     "wilson_version": (ctypes.c_char_p, []),
@@ -240,6 +242,16 @@ def wilson_gauge_detach_clover(ctx, g):
 
 def wilson_dslash_ex(ctx, g, out, in_, kappa, parity, precision=WILSON_FP64, nrhs=1):
     return lib().wilson_dslash_ex(ctx, g, _ptr(out), _ptr(in_), float(kappa), int(parity), int(precision), int(nrhs))
+
+
+def wilson_layout_hop(ctx, out, in_, U, dims, kappa, parity, precision, layout, link_reals=18, reps=0):
+    """Returns (status, mean microseconds of the `reps` timed launches)."""
+    d = _dims(dims)
+    _check_size(out, d, 1, "out"); _check_size(in_, d, 1, "in"); _check_size(U, d, 1, "U", per_site=72)
+    us = ctypes.c_double(0.0)
+    st = lib().wilson_layout_hop(ctx, _ptr(out), _ptr(in_), _ptr(U), d.ctypes.data, float(kappa), int(parity),
+                                 int(precision), int(layout), int(link_reals), int(reps), ctypes.byref(us))
+    return st, us.value
 
 
 def wilson_solve_ex(ctx, g, x, b, nrhs, kappa, tol, opts=None):

@@ -6,6 +6,7 @@
 #include <mutex>
 #include <new>
 
+#include "layout_lab.h"
 #include "runtime.h"
 #include "solver.h"
 #include "wilson.h"
@@ -476,6 +477,65 @@ int wilson_timing_read(wilson_ctx *ctx, int32_t kernel_class, double *total_ms, 
     if (total_ms) *total_ms = ctx->t_ms[kernel_class];
     if (launches) *launches = ctx->launches[kernel_class];
     if (bytes) *bytes = ctx->t_bytes[kernel_class];
+    return WILSON_OK;
+    API_END
+}
+
+int wilson_layout_hop(wilson_ctx *ctx, double *out, const double *in, const double *U, const int32_t dims[4],
+                      double kappa, int32_t parity, int32_t precision, int32_t layout, int32_t link_reals,
+                      int32_t reps, double *us_per_launch) {
+    API_BEGIN
+    WL_CHECK_ARG(ctx && out && in && U, "NULL argument");
+    WL_CHECK_ARG(is_device_ptr(out) && is_device_ptr(in) && is_device_ptr(U), "layout hop needs device pointers");
+    check_dims(dims);
+    WL_CHECK_ARG(parity == 0 || parity == 1, "parity must be 0 or 1");
+    WL_CHECK_ARG(precision == WILSON_FP64 || precision == WILSON_FP32, "precision must be WILSON_FP64 or WILSON_FP32");
+    WL_CHECK_ARG(layout >= 0 && layout < LAB_LAYOUT_COUNT, "unknown layout");
+    WL_CHECK_ARG(link_reals == 12 || link_reals == 18, "link_reals must be 12 or 18");
+    WL_CHECK_ARG(reps >= 0 && reps <= 100000, "reps out of range");
+    WL_CHECK_ARG(std::isfinite(kappa), "kappa must be finite");
+    LabGeom g;
+    WL_CHECK_ARG(lab_geom(g, dims, layout), "extents not allowed for this layout (sub-lattice layout: Ly, Lz, Lt "
+                                            "multiples of 8)");
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+    hipStream_t s = ctx->stream;
+    if (link_reals == 12) {
+        if (ctx->flag.size() < sizeof(int)) ctx->flag.alloc(256);
+        static const int zero = 0;
+        WL_HIP(hipMemcpyAsync(ctx->flag.get(), &zero, sizeof(int), hipMemcpyHostToDevice, s));
+        WL_HIP(launch_su3_check(U, V * 4, 1e-13, ctx->flag.as<int>(), s));
+        int bad = 0;
+        WL_HIP(hipMemcpyAsync(&bad, ctx->flag.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+        WL_HIP(hipStreamSynchronize(s));
+        WL_CHECK_ARG(!bad, "link_reals 12 needs SU(3) links");
+    }
+    DevBuf fin(lab_spinor_bytes(g, precision)), fout(lab_spinor_bytes(g, precision));
+    DevBuf u0(lab_link_bytes(g, precision, link_reals)), u1(lab_link_bytes(g, precision, link_reals));
+    WL_HIP(launch_lab_pack_spinor(fin.get(), in, g, layout, precision, 1 - parity, s));
+    WL_HIP(launch_lab_pack_links(u0.get(), U, g, layout, precision, link_reals, 0, s));
+    WL_HIP(launch_lab_pack_links(u1.get(), U, g, layout, precision, link_reals, 1, s));
+    WL_HIP(launch_lab_hop(fout.get(), fin.get(), u0.get(), u1.get(), g, layout, precision, link_reals, parity, -kappa, s));
+    double us = 0.0;
+    if (reps > 0) {
+        hipEvent_t e0, e1;
+        WL_HIP(hipEventCreate(&e0));
+        WL_HIP(hipEventCreate(&e1));
+        WL_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; r++)
+            WL_HIP(launch_lab_hop(fout.get(), fin.get(), u0.get(), u1.get(), g, layout, precision, link_reals, parity,
+                                  -kappa, s));
+        WL_HIP(hipEventRecord(e1, s));
+        WL_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        WL_HIP(hipEventDestroy(e0));
+        WL_HIP(hipEventDestroy(e1));
+        us = 1000.0 * ms / reps;
+    }
+    WL_HIP(launch_lab_zero(out, V * 24, s));
+    WL_HIP(launch_lab_unpack_spinor(out, fout.get(), g, layout, precision, parity, s));
+    WL_HIP(hipStreamSynchronize(s));
+    if (us_per_launch) *us_per_launch = us;
     return WILSON_OK;
     API_END
 }

@@ -29,14 +29,16 @@ def _find(d, suffix):
 
 
 def short_name(name):
-    n = name.replace("void ", "")
+    n = name.replace("void ", "").replace("(anonymous namespace)::", "")
     return n.split("(")[0][:70]
 
 
-def stats(d, out, command, top=14):
+def stats(d, out, command, top=14, match=None):
     rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
+    if match:  # only the kernels whose name contains `match` (percentages stay of the whole run)
+        rows = [r for r in rows if match in r["Name"]]
     lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
              f"{'calls':>7} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
     for r in rows[:top]:
@@ -89,6 +91,35 @@ def traffic(workload, fetch_dir, write_dir, out, command, first, kernel_substr="
     return rec
 
 
+def kernel_traffic(fetch_dir, write_dir, match, out, command):
+    """FETCH_SIZE / WRITE_SIZE per dispatch, averaged over every dispatch of each kernel whose
+    name contains `match`, calibrated by the copy probe of the same runs; one record per
+    kernel name, written to `out` (a text table)."""
+    def per_kernel(d):
+        rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+        acc, copy = {}, []
+        for r in rows:
+            if "stream_copy_kernel" in r["Kernel_Name"]:
+                copy.append(float(r["Counter_Value"]))
+            elif match in r["Kernel_Name"]:
+                acc.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        if not copy or not acc:
+            raise ValueError(f"{d}: no '{match}' kernels or no copy probe")
+        return {k: sum(v) / len(v) for k, v in acc.items()}, COPY_BYTES / (sum(copy) / len(copy) * 1024)
+    f, fs = per_kernel(fetch_dir)
+    w, ws = per_kernel(write_dir)
+    lines = ["# rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch (two separate --pmc runs)",
+             f"# command: {command}",
+             f"# calibration: bytes per counted byte, from the 2 GiB copy probe of the same runs: "
+             f"fetch {fs:.4f}, write {ws:.4f}", "",
+             f"{'fetch_GB':>9} {'write_GB':>9}  kernel"]
+    for k in sorted(f, key=lambda k: -f[k]):
+        lines.append(f"{f[k] * 1024 * fs / 1e9:9.3f} {w.get(k, float('nan')) * 1024 * ws / 1e9:9.3f}  {k}")
+    text = "\n".join(lines) + "\n"
+    open(out, "w").write(text)
+    return text
+
+
 def main():
     p = argparse.ArgumentParser()
     sub = p.add_subparsers(dest="cmd", required=True)
@@ -96,6 +127,14 @@ def main():
     a.add_argument("--dir", required=True)
     a.add_argument("--out", required=True)
     a.add_argument("--command", required=True)
+    a.add_argument("--top", type=int, default=14, help="kernels listed (by total time)")
+    a.add_argument("--match", default=None, help="list only kernels whose name contains this")
+    c = sub.add_parser("kernel-traffic")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--match", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
     b = sub.add_parser("traffic")
     b.add_argument("--workload", required=True)
     b.add_argument("--fetch", required=True)
@@ -106,7 +145,9 @@ def main():
                    help="plain-hop dispatches at the start (bench.py: 3 warm-up + --dslash-reps)")
     args = p.parse_args()
     if args.cmd == "stats":
-        print(stats(args.dir, args.out, args.command))
+        print(stats(args.dir, args.out, args.command, args.top, args.match))
+    elif args.cmd == "kernel-traffic":
+        print(kernel_traffic(args.fetch, args.write, args.match, args.out, args.command))
     else:
         print(json.dumps(traffic(args.workload, args.fetch, args.write, args.out, args.command, args.first), indent=1))
 
