@@ -182,9 +182,11 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
             }
         reconstruct<MU, FWD, R>(acc[r], u);
     }
-    // keep the next direction's gathers from being hoisted above this one: with all eight
-    // directions in flight at once the kernel needs more registers than it can keep
-    __builtin_amdgcn_sched_barrier(0);
+    // directions go in two groups (x and y, then z and t): the loads of a group may overlap,
+    // and a barrier after each group keeps later gathers from being hoisted into it (all
+    // eight directions in flight need more registers than the budget; one direction at a
+    // time measured 1.5 % slower in FP64)
+    if constexpr ((MU == 1 || MU == 3) && !FWD) __builtin_amdgcn_sched_barrier(0);
 }
 
 // One output site i (all RPT right-hand sides of this lane): gather, project, multiply,
