@@ -34,6 +34,8 @@ def parse():
     p.add_argument("--dslash-reps", type=int, default=50)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--inner-tol", type=float, default=0.0,
+                   help="mixed precision: residual drop per cycle (0: the library's default)")
     p.add_argument("--dslash-only", action="store_true", help="only the Dslash section and the copy probe")
     p.add_argument("--requests", type=int, default=60, help="serving: requests per phase")
     p.add_argument("--loads", type=lambda v: [float(x) for x in v.split(",")], default=[0.5, 0.8, 1.0],
@@ -95,8 +97,15 @@ WORKLOADS = {
                  "clover matrix D_W + F, plain FP64 even-odd BiCGStab, 32^3x64, kappa=0.125, synthetic F (c=0.05)"),
     "clover32_mixed": ((32, 32, 32, 64), 0.125, 1e-10, 1, 1,
                        "clover matrix D_W + F, mixed precision (FP32 inner, FP64 outer), 32^3x64, kappa=0.125"),
+    "mixed48_reliable": ((48, 48, 48, 96), 0.125, 1e-10, 1, 1,
+                         "mixed precision with reliable updates (FP32 inner recurrence kept across FP64 residual "
+                         "replacements), 48^3x96, kappa=0.125, tol=1e-10"),
+    "mixed48_fp16_reliable": ((48, 48, 48, 96), 0.125, 1e-10, 3, 1,
+                              "mixed precision with reliable updates (FP16 spinors + per-site scale, FP32 links), "
+                              "48^3x96, kappa=0.125, tol=1e-10"),
 }
 CLOVER = {"clover32", "clover32_mixed"}
+RELIABLE = {"mixed48_reliable", "mixed48_fp16_reliable"}
 
 
 def run_serving(args):
@@ -495,7 +504,8 @@ def main():
         L.check(L.wilson_gauge_attach_clover(ctx, g, F, dims), "attach clover")
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-    opts = {"precision": precision, "maxiter": 20000}
+    opts = {"precision": precision, "maxiter": 20000, "mixed_update": 1 if args.workload in RELIABLE else 0,
+            "inner_tol": args.inner_tol}
 
     # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload);
     # for the clover matrix the hops of D_clov on both parities (T x - kappa H x) ----
@@ -673,7 +683,7 @@ def main():
     fp64_same = None
     if precision != 0:
         f_lat, f_it = [], []
-        fopts = dict(opts, precision=0)
+        fopts = dict(opts, precision=0, mixed_update=0)
         x.zero_()
         L.check(L.wilson_solve_ex(ctx, g, x, srcs[0], nrhs, kap, tl, fopts)[0], "FP64 warm-up solve")
         torch.cuda.synchronize()

@@ -97,6 +97,12 @@ typedef struct {
                               1e-5 for FP32, 1e-2 for FP16) */
     int32_t use_x0;        /* nonzero: x holds the initial guess on entry */
     int32_t poll_every;    /* iterations between host convergence polls (<=0: default) */
+    int32_t mixed_update;  /* mixed precision with BiCGStab: 0 defect correction (each cycle
+                              restarts the inner solve on the normalised FP64 residual),
+                              1 reliable updates (Sleijpen and van der Vorst 1996: one inner
+                              recurrence through all cycles; at each cycle the FP64 residual
+                              replaces the iterated one; inner_tol is the drop per cycle
+                              with the same defaults).  Batches take 0. */
 } wilson_solve_opts;
 
 typedef struct {

@@ -47,7 +47,7 @@ EXPORTS = [
 class wilson_solve_opts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32), ("maxiter", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int32),
-                ("poll_every", ctypes.c_int32)]
+                ("poll_every", ctypes.c_int32), ("mixed_update", ctypes.c_int32)]
 
 
 class wilson_solve_info(ctypes.Structure):
@@ -175,6 +175,7 @@ def _opts(opts):
     o.inner_tol = float(opts.get("inner_tol", 0.0))
     o.use_x0 = int(bool(opts.get("use_x0", False)))
     o.poll_every = int(opts.get("poll_every", 0))
+    o.mixed_update = int(opts.get("mixed_update", 0))
     return ctypes.byref(o)
 
 

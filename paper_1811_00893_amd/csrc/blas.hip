@@ -317,19 +317,25 @@ __device__ void fin_op(RhsState *st, const double a0, const double a1, const dou
         st->r2 = a0;
         st->iter += 1;
         if (!finite(a0)) { fail(FAIL_NONFINITE); return; }
-        if (st->phase == PH_SCONV || a0 <= st->stop2) { st->phase = PH_DONE; return; }
+        const bool stop = st->phase == PH_SCONV || a0 <= st->stop2;
         const double rn = sqrt(a1 * a1 + a2 * a2);
-        if (!(rn > 1e-30 * sqrt(st->rhat2 * a0))) { fail(FAIL_BREAKDOWN); return; }
-        // beta = (rho'/rho) (alpha/omega)
-        const double d1 = st->rho_re * st->rho_re + st->rho_im * st->rho_im;
-        const double q1r = (a1 * st->rho_re + a2 * st->rho_im) / d1, q1i = (a2 * st->rho_re - a1 * st->rho_im) / d1;
-        const double d2 = st->omega_re * st->omega_re + st->omega_im * st->omega_im;
-        const double q2r = (st->alpha_re * st->omega_re + st->alpha_im * st->omega_im) / d2;
-        const double q2i = (st->alpha_im * st->omega_re - st->alpha_re * st->omega_im) / d2;
-        st->beta_re = q1r * q2r - q1i * q2i;
-        st->beta_im = q1r * q2i + q1i * q2r;
-        st->rho_re = a1;
-        st->rho_im = a2;
+        if (st->phase != PH_SCONV && rn > 1e-30 * sqrt(st->rhat2 * a0)) {
+            // beta = (rho'/rho) (alpha/omega); also on the last iteration of a cycle, so that
+            // a recurrence resumed after its residual was replaced continues from here
+            const double d1 = st->rho_re * st->rho_re + st->rho_im * st->rho_im;
+            const double q1r = (a1 * st->rho_re + a2 * st->rho_im) / d1, q1i = (a2 * st->rho_re - a1 * st->rho_im) / d1;
+            const double d2 = st->omega_re * st->omega_re + st->omega_im * st->omega_im;
+            const double q2r = (st->alpha_re * st->omega_re + st->alpha_im * st->omega_im) / d2;
+            const double q2i = (st->alpha_im * st->omega_re - st->alpha_re * st->omega_im) / d2;
+            st->beta_re = q1r * q2r - q1i * q2i;
+            st->beta_im = q1r * q2i + q1i * q2r;
+            st->rho_re = a1;
+            st->rho_im = a2;
+        } else if (!stop) {
+            fail(FAIL_BREAKDOWN);
+            return;
+        }
+        if (stop) st->phase = PH_DONE;
     } else if constexpr (OP == FIN_CG_R2) {
         st->r2 = a0;
         st->fail = FAIL_NONE;

@@ -142,6 +142,9 @@ static void check_solve_args(const double *kappa, const double *tol, int nrhs, c
         WL_CHECK_ARG(o->solver == WILSON_SOLVER_BICGSTAB_EO || o->solver == WILSON_SOLVER_CGNR_EO, "unknown solver");
         WL_CHECK_ARG(o->precision >= WILSON_FP64 && o->precision <= WILSON_FP16_L32, "unknown precision");
         WL_CHECK_ARG(o->maxiter > 0, "maxiter must be > 0");
+        WL_CHECK_ARG(o->mixed_update == 0 || o->mixed_update == 1, "mixed_update must be 0 or 1");
+        WL_CHECK_ARG(o->mixed_update == 0 || (o->precision != WILSON_FP64 && o->solver == WILSON_SOLVER_BICGSTAB_EO),
+                     "reliable updates need a mixed precision and BiCGStab");
     }
 }
 
@@ -156,6 +159,7 @@ static SolveParams params_from(const wilson_solve_opts *o, int maxiter_default) 
         p.inner_tol = o->inner_tol;
         p.use_x0 = o->use_x0 != 0;
         p.poll_every = o->poll_every > 0 ? o->poll_every : 1;
+        p.reliable = o->mixed_update == 1;
     }
     return p;
 }
@@ -397,6 +401,7 @@ int wilson_batch_create(wilson_ctx *ctx, const wilson_gauge *g, int32_t nslots, 
     if (opts) {
         double k = 0.1, t = 1e-10;
         check_solve_args(&k, &t, 1, opts);
+        WL_CHECK_ARG(opts->mixed_update == 0, "batches use defect correction (mixed_update 0)");
     }
     *batch = reinterpret_cast<wilson_batch *>(batch_create(ctx, g, nslots, params_from(opts, 10000)));
     return WILSON_OK;

@@ -210,8 +210,9 @@ hipError_t launch_from_parity(double *canon, Spinor f, const Geom &g, int par, i
 // dst (prec) = scale * src (FP64 parity field); nrhs fields; scale per rhs from state->aux if use_state.
 hipError_t launch_convert(Spinor dst, Spinor src, const Geom &g, int nrhs, const RhsState *state, int inv_sqrt_aux,
                           hipStream_t s);
-// x64 += c[rhs] * e (any precision), c from state->aux (sqrt) per rhs.
-hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const RhsState *state, hipStream_t s);
+// x64 += c[rhs] * e (any precision): c = sqrt(state[rhs].aux) with sqrt_aux, else 1.
+hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const RhsState *state, int sqrt_aux,
+                           hipStream_t s);
 // Gauge: canonical complex128 links -> parity-split planes in precision prec.
 // recon 18: all 9 entries, t-boundary sign folded in; recon 12: rows 0 and 1 only, no sign.
 hipError_t launch_gauge_pack(void *dst, int prec, const double *canon, const Geom &g, int recon, hipStream_t s);

@@ -79,12 +79,16 @@ __global__ void __launch_bounds__(256) convert_kernel(Spinor dst, Spinor src, Ge
 }
 
 template <int PE>
-__global__ void __launch_bounds__(256) axpy_f64_kernel(Spinor x, Spinor e, Geom g, const RhsState *state) {
+__global__ void __launch_bounds__(256) axpy_f64_kernel(Spinor x, Spinor e, Geom g, const RhsState *state,
+                                                       int sqrt_aux) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.Vh) return;
     const int rhs = blockIdx.y;
-    const double a = state[rhs].aux;
-    const double c = a > 0.0 ? sqrt(a) : 0.0;
+    double c = 1.0;
+    if (sqrt_aux) {
+        const double a = state[rhs].aux;
+        c = a > 0.0 ? sqrt(a) : 0.0;
+    }
     using R = real_t<PE>;
     Cx<R> ev[12];
     load_site<PE, R>(ev, e, g.stride, rhs, i);
@@ -223,13 +227,14 @@ hipError_t launch_convert(Spinor dst, Spinor src, const Geom &g, int nrhs, const
     return hipGetLastError();
 }
 
-hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const RhsState *state, hipStream_t s) {
-    if (x64.prec != P64) return hipErrorInvalidValue;
+hipError_t launch_axpy_f64(Spinor x64, Spinor e, const Geom &g, int nrhs, const RhsState *state, int sqrt_aux,
+                           hipStream_t s) {
+    if (x64.prec != P64 || (sqrt_aux && !state)) return hipErrorInvalidValue;
     const dim3 grid = site_grid(g, nrhs), block(256);
     switch (e.prec) {
-        case P64: hipLaunchKernelGGL(axpy_f64_kernel<P64>, grid, block, 0, s, x64, e, g, state); break;
-        case P32: hipLaunchKernelGGL(axpy_f64_kernel<P32>, grid, block, 0, s, x64, e, g, state); break;
-        case P16: hipLaunchKernelGGL(axpy_f64_kernel<P16>, grid, block, 0, s, x64, e, g, state); break;
+        case P64: hipLaunchKernelGGL(axpy_f64_kernel<P64>, grid, block, 0, s, x64, e, g, state, sqrt_aux); break;
+        case P32: hipLaunchKernelGGL(axpy_f64_kernel<P32>, grid, block, 0, s, x64, e, g, state, sqrt_aux); break;
+        case P16: hipLaunchKernelGGL(axpy_f64_kernel<P16>, grid, block, 0, s, x64, e, g, state, sqrt_aux); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -271,18 +271,25 @@ class EoCore {
     // ---- inner Krylov solve on M_ee x = rhs (rhs in P, x in PX) ----
     // active[k]: which RHS take part; stop2[k]: (tol * norm)^2 of the iterated residual.
     // Returns per-RHS final states.
+    // resume (BiCGStab only): the states to continue from, with phase, stop2 and iter set by
+    // the caller, who has also replaced the iterated residual r; no initialisation runs and
+    // the recurrence (p, v, rhat, rho, alpha, omega, beta) carries on.
     std::vector<RhsState> inner_solve(Spinor rhs, Spinor x, bool use_x0, const std::vector<char> &active,
-                                      const std::vector<double> &stop2, int maxiter, int poll_every) {
+                                      const std::vector<double> &stop2, int maxiter, int poll_every,
+                                      const std::vector<RhsState> *resume = nullptr) {
         std::vector<RhsState> h(nk);
         for (int k = 0; k < nk; k++) {
             std::memset(&h[k], 0, sizeof(RhsState));
             h[k].phase = active[k] ? PH_RUN : PH_IDLE;
             h[k].stop2 = stop2[k];
         }
+        if (resume) h = *resume;
         upload_states(sin(), h);
         const int nb = blas_nblocks(g, P);
         Spinor none;
-        if (method == WILSON_SOLVER_BICGSTAB_EO) {
+        if (resume) {
+            if (method != WILSON_SOLVER_BICGSTAB_EO) throw Error(WILSON_INVALID_ARG, "only BiCGStab resumes");
+        } else if (method == WILSON_SOLVER_BICGSTAB_EO) {
             // r = rhs - M x  (or rhs), rhat = r
             if (use_x0) {
                 apply_M(r.f, x, tmp.f, false, RED_NONE, none, sin(), PH_RUN, &rhs);
@@ -531,6 +538,86 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
             use_x0 = true;
             checked = false;
         }
+    } else if (prm.reliable) {
+        // Reliable updates (Sleijpen and van der Vorst, 1996): one low-precision BiCGStab
+        // recurrence runs through every cycle.  A cycle ends when the iterated residual has
+        // dropped by delta; then the low-precision solution increment is added to the FP64
+        // solution, the FP64 residual b' - M x is recomputed and replaces the iterated
+        // residual, and the recurrence goes on with its search directions and scalars.  The
+        // fields are not rescaled between cycles (FP32 and per-site-scaled FP16 keep the
+        // range of a 1e-10 relative residual).
+        const double delta = prm.inner_tol > 0 ? prm.inner_tol : (C.P == P32 ? 1e-5 : 1e-2);
+        C.outer_residual();
+        std::vector<RhsState> h = C.read_states(C.sout());
+        std::vector<double> prev(nrhs, 0.0), inner_stop(nrhs, 0.0);
+        std::vector<int> stall(nrhs, 0);
+        for (int k = 0; k < nrhs; k++) prev[k] = h[k].aux;
+        std::vector<RhsState> rec;  // the recurrence to resume (empty: start one)
+        const int max_cycles = 400;
+        for (int cyc = 0; cyc < max_cycles; cyc++) {
+            std::vector<char> active(nrhs);
+            for (int k = 0; k < nrhs; k++) {
+                if (done[k]) { active[k] = 0; continue; }
+                const double rr = h[k].aux;
+                if (!std::isfinite(rr)) { status[k] = WILSON_NONFINITE; done[k] = 1; active[k] = 0; continue; }
+                if (rr <= stop2[k]) { done[k] = 2; active[k] = 0; continue; }  // confirmed below
+                active[k] = 1;
+                inner_stop[k] = std::max(delta * delta * rr, 0.25 * stop2[k]);
+            }
+            if (std::none_of(active.begin(), active.end(), [](char c) { return c; })) break;
+            const int budget = prm.maxiter - used;
+            if (budget <= 0) break;
+            // a recurrence that ended on a failure, or on |s| (omega = 0), cannot go on
+            bool fresh = rec.empty();
+            for (int k = 0; k < nrhs && !fresh; k++)
+                if (active[k] && (rec[k].phase == PH_FAIL || (rec[k].omega_re == 0.0 && rec[k].omega_im == 0.0)))
+                    fresh = true;
+            WL_HIP(launch_zero(C.xin.f, g, nrhs, ctx->stream));
+            std::vector<RhsState> fin;
+            if (fresh) {
+                WL_HIP(launch_convert(C.rf.f, C.r64.f, g, nrhs, C.sout(), 0, ctx->stream));
+                fin = C.inner_solve(C.rf.f, C.xin.f, false, active, inner_stop, budget, prm.poll_every);
+            } else {
+                WL_HIP(launch_convert(C.r.f, C.r64.f, g, nrhs, C.sout(), 0, ctx->stream));  // r <- true residual
+                for (int k = 0; k < nrhs; k++) {
+                    rec[k].phase = active[k] ? PH_RUN : PH_IDLE;
+                    rec[k].stop2 = inner_stop[k];
+                    rec[k].r2 = h[k].aux;
+                    rec[k].iter = 0;
+                    rec[k].fail = FAIL_NONE;
+                }
+                fin = C.inner_solve(C.rf.f, C.xin.f, false, active, inner_stop, budget, prm.poll_every, &rec);
+            }
+            rec = fin;
+            int mx = 0;
+            for (int k = 0; k < nrhs; k++)
+                if (active[k]) {
+                    iters[k] += fin[k].iter;
+                    cycles[k] += 1;
+                    mx = std::max(mx, fin[k].iter);
+                    if (fin[k].phase == PH_FAIL && fin[k].fail == FAIL_NONFINITE) {
+                        status[k] = WILSON_NONFINITE;
+                        done[k] = 1;
+                    }
+                }
+            used += std::max(mx, 1);
+            WL_HIP(launch_axpy_f64(C.x_e.f, C.xin.f, g, nrhs, C.sout(), 0, ctx->stream));
+            C.outer_residual();
+            h = C.read_states(C.sout());
+            for (int k = 0; k < nrhs; k++) {
+                if (!active[k] || done[k]) continue;
+                // no progress over 8 cycles in a row: give up
+                stall[k] = h[k].aux > 0.9 * prev[k] ? stall[k] + 1 : 0;
+                if (stall[k] >= 8) { status[k] = WILSON_NOT_CONVERGED; done[k] = 1; }
+                prev[k] = h[k].aux;
+            }
+        }
+        true_check();
+        for (int k = 0; k < nrhs; k++) {
+            if (status[k] == WILSON_NONFINITE) continue;
+            if (bn2[k] == 0.0 || res2[k] <= stop2[k]) status[k] = WILSON_OK;
+            else status[k] = WILSON_NOT_CONVERGED;
+        }
     } else {
         // FP64 defect correction on the even system around low-precision inner solves
         const double delta = prm.inner_tol > 0 ? prm.inner_tol : (C.P == P32 ? 1e-5 : 1e-2);
@@ -565,7 +652,7 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
                     mx = std::max(mx, fin[k].iter);
                 }
             used += std::max(mx, 1);
-            WL_HIP(launch_axpy_f64(C.x_e.f, C.xin.f, g, nrhs, C.sout(), ctx->stream));
+            WL_HIP(launch_axpy_f64(C.x_e.f, C.xin.f, g, nrhs, C.sout(), 1, ctx->stream));
             C.outer_residual();
             h = C.read_states(C.sout());
             for (int k = 0; k < nrhs; k++) {
@@ -865,7 +952,7 @@ class BatchEngine {
             // mixed: fold the correction into x (FP64), new FP64 residual
             s.cycles++;
             C->select(k, 1);
-            WL_HIP(launch_axpy_f64(C->V(C->x_e.f), C->V(C->xin.f), C->g, 1, C->S(C->sout()), ctx->stream));
+            WL_HIP(launch_axpy_f64(C->V(C->x_e.f), C->V(C->xin.f), C->g, 1, C->S(C->sout()), 1, ctx->stream));
             C->outer_residual();
             const double r2 = C->read_states(C->sout())[0].aux;
             C->select_all();

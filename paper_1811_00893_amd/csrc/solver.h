@@ -33,6 +33,7 @@ struct SolveParams {
     double inner_tol = 0.0;
     bool use_x0 = false;
     int poll_every = 1;
+    bool reliable = false;  // mixed precision: reliable updates instead of defect correction
 };
 
 // Solves for nrhs right-hand sides given in canonical layout on the device.
