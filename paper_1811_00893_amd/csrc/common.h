@@ -168,6 +168,7 @@ struct LaunchCfg {
     int lds_kb = 0;    // >0: reserve this much LDS per block to cap blocks per CU (waves in flight)
     int wsplit = 0;    // 1: the waves of a block take successive RHS groups of the same 64 sites
     int shx = 0;       // 1: x/y neighbours shuffled from the lanes that loaded them (RPT 1)
+    int dsplit = 0;    // 1: five waves per 64-site tile, wave 1 + mu on direction mu (block 320, RPT 1)
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----

@@ -10,6 +10,8 @@ hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
 
 // ---------------------------------------------------------------------------------
 bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
+    if (c.dsplit)  // one RHS per block, five waves, memory-order tiles of 64 sites
+        return c.dsplit == 1 && c.block == 320 && c.rpt == 1 && !c.shx && !c.wsplit && c.zblk == 0 && c.lds_kb == 0;
     if (c.rpt < 1 || c.rpt > 4) return false;
     if (c.shx && c.rpt != 1) return false;  // with more RHS per lane the exchange spills
     if (a.clov_mode != CLV_NONE && (c.rpt != 1 || c.shx)) return false;  // clover kernels: one RHS per lane
@@ -29,7 +31,7 @@ bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
 
 // Number of site tiles of a launch (the row length of the partial sums it writes).
 int hop_nblocks(const HopArgs &a, const LaunchCfg &c) {
-    const int tile = c.wsplit ? 64 : c.block;
+    const int tile = c.wsplit || c.dsplit ? 64 : c.block;
     return (a.g.Vh + tile - 1) / tile;
 }
 

@@ -249,6 +249,68 @@ __device__ __forceinline__ void lane_nbr(Cx<real_t<SP>> (&H)[RPT][2][3], const C
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Epilogue of one output site and right-hand side: gamma5 on the hop result, the factor
+// cH, the y and z terms (with the clover modes), the store and the site's reduction terms.
+// PRE (bits 1, 2, 4): y, z, the dot partner w are already in yv, zv, wv (loaded by the
+// caller); the others are loaded here.
+template <int SP, bool CLV, int PRE>
+__device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, int rhs,
+                                           const Cx<real_t<SP>> (&acc)[4][3], Cx<real_t<SP>> (&yv)[12],
+                                           Cx<real_t<SP>> (&zv)[12], Cx<real_t<SP>> (&wv)[12], double (&red)[3]) {
+    using R = real_t<SP>;
+    const int stride = a.g.stride;
+    constexpr int CP = SP == P64 ? P64 : P32;  // storage precision of clover blocks
+    const R cH = (R)a.cH[rhs];
+    Cx<R> o[12];
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            // gamma5 on the hop result: (g5 v)_s = -v_{s^2}
+            Cx<R> v = a.g5out ? Cx<R>{-acc[s ^ 2][k].re, -acc[s ^ 2][k].im} : acc[s][k];
+            o[s * 3 + k] = cscale(v, cH);
+        }
+    if (a.has_y) {
+        if (!(PRE & 1)) load_site<SP, R>(yv, a.y, stride, rhs, i);
+        if (CLV && a.clov_mode == CLV_Y) {  // T y enters the sum; y itself stays the dot partner
+            Cx<R> ty[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) ty[k] = yv[k];
+            clov_apply<CP, R>(ty, a.clov, stride, i);
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], ty[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], yv[k]);
+        }
+    }
+    if (CLV && a.clov_mode == CLV_ALL) clov_apply<CP, R>(o, a.clov, stride, i);
+    if (a.has_z) {
+        if (!(PRE & 2)) load_site<SP, R>(zv, a.z, stride, rhs, i);
+        if (CLV && a.clov_mode == CLV_Z) clov_apply<CP, R>(zv, a.clov, stride, i);
+        const R cz = (R)a.cz;
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
+    }
+    if (valid && !a.nostore) store_site<SP, R>(a.out, stride, rhs, i, o);
+    if (!valid || a.red == RED_NONE) return;
+    if (a.red == RED_NORM2) {
+        for (int k = 0; k < 12; k++) red[0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+    } else if (a.red == RED_DOT) {
+        if (!(PRE & 4)) load_site<SP, R>(wv, a.w, stride, rhs, i);
+        for (int k = 0; k < 12; k++) {  // <w, o> = sum conj(w) o
+            red[0] += (double)wv[k].re * o[k].re + (double)wv[k].im * o[k].im;
+            red[1] += (double)wv[k].re * o[k].im - (double)wv[k].im * o[k].re;
+        }
+    } else {
+        for (int k = 0; k < 12; k++) {  // <o, y> and |o|^2
+            red[0] += (double)o[k].re * yv[k].re + (double)o[k].im * yv[k].im;
+            red[1] += (double)o[k].re * yv[k].im - (double)o[k].im * yv[k].re;
+            red[2] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        }
+    }
+}
+
 template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV>
 __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, int r0, const bool (&act)[RPT],
                                          double (&red)[RPT][3]) {
@@ -304,63 +366,11 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true>(acc, a, act, r0, tp, par, i, sgn_tf, stride);
     hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride);
 
-    constexpr int CP = SP == P64 ? P64 : P32;  // storage precision of clover blocks
 #pragma unroll
     for (int r = 0; r < RPT; r++) {
         if (RPT > 1 && !act[r]) continue;
-        const int rhs = r0 + r;
-        const R cH = (R)a.cH[rhs];
-        Cx<R> o[12];
-#pragma unroll
-        for (int s = 0; s < 4; s++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                // gamma5 on the hop result: (g5 v)_s = -v_{s^2}
-                Cx<R> v = a.g5out ? Cx<R>{-acc[r][s ^ 2][k].re, -acc[r][s ^ 2][k].im} : acc[r][s][k];
-                o[s * 3 + k] = cscale(v, cH);
-            }
-        Cx<R> yv[12];
-        if (a.has_y) {
-            load_site<SP, R>(yv, a.y, stride, rhs, i);
-            if (CLV && a.clov_mode == CLV_Y) {  // T y enters the sum; y itself stays the dot partner
-                Cx<R> ty[12];
-#pragma unroll
-                for (int k = 0; k < 12; k++) ty[k] = yv[k];
-                clov_apply<CP, R>(ty, a.clov, stride, i);
-#pragma unroll
-                for (int k = 0; k < 12; k++) o[k] = cadd(o[k], ty[k]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; k++) o[k] = cadd(o[k], yv[k]);
-            }
-        }
-        if (CLV && a.clov_mode == CLV_ALL) clov_apply<CP, R>(o, a.clov, stride, i);
-        if (a.has_z) {
-            Cx<R> zv[12];
-            load_site<SP, R>(zv, a.z, stride, rhs, i);
-            if (CLV && a.clov_mode == CLV_Z) clov_apply<CP, R>(zv, a.clov, stride, i);
-            const R cz = (R)a.cz;
-#pragma unroll
-            for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
-        }
-        if (valid && !a.nostore) store_site<SP, R>(a.out, stride, rhs, i, o);
-        if (!valid || a.red == RED_NONE) continue;
-        if (a.red == RED_NORM2) {
-            for (int k = 0; k < 12; k++) red[r][0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-        } else if (a.red == RED_DOT) {
-            Cx<R> wv[12];
-            load_site<SP, R>(wv, a.w, stride, rhs, i);
-            for (int k = 0; k < 12; k++) {  // <w, o> = sum conj(w) o
-                red[r][0] += (double)wv[k].re * o[k].re + (double)wv[k].im * o[k].im;
-                red[r][1] += (double)wv[k].re * o[k].im - (double)wv[k].im * o[k].re;
-            }
-        } else {
-            for (int k = 0; k < 12; k++) {  // <o, y> and |o|^2
-                red[r][0] += (double)o[k].re * yv[k].re + (double)o[k].im * yv[k].im;
-                red[r][1] += (double)o[k].re * yv[k].im - (double)o[k].im * yv[k].re;
-                red[r][2] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-            }
-        }
+        Cx<R> yv[12], zv[12], wv[12];
+        hop_finish<SP, CLV, 0>(a, i, valid, r0 + r, acc[r], yv, zv, wv, red[r]);
     }
 }
 
@@ -439,6 +449,107 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     }
 }
 
+// Lattices too small to fill the GPU: with one wave per 64 sites most of it idles, and a
+// wave's time is its chain of dependent gathers.  Here five waves share a tile of 64
+// sites (one right-hand side per block): wave 1 + mu does the two hops along mu and leaves
+// its sum in LDS, while wave 0 loads the epilogue's y; after the barrier wave 0
+// adds the four sums in a fixed order (x, y, z, t) and finishes the sites.  Partial sums
+// of the reductions: one per tile, from wave 0.
+template <int SP, int GP, int NE, bool G5, bool LNT, bool CLV>
+__global__ void __launch_bounds__(320) hop_kernel_ds(const HopArgs a, int xcd_remap) {
+    using R = real_t<SP>;
+    const Geom &g = a.g;
+    const int stride = g.stride;
+    const int lb = xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tile = lb / a.nrhs, rhs = lb - tile * a.nrhs;
+    const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    if (a.state != nullptr && !(a.state[rhs].phase & a.run_mask)) return;  // uniform over the block
+    const int l = tile * 64 + lane;
+    const bool valid = l < g.Vh;
+    const int i = valid ? l : g.Vh - 1;
+    __shared__ R part[4][24][64];
+    Cx<R> yv[12], zv[12], wd[12];
+    if (wv > 0) {
+        const bool act[1] = {true};
+        Cx<R> acc[1][4][3];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc[0][s][k] = {R(0), R(0)};
+        const int par = a.par, opar = 1 - par;
+        const SiteXY c = cb_coords(g, i, par);
+        const R one = R(1);
+        if (wv == 1) {
+            const int row = i - c.xh;
+            const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
+            const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 0, true>(acc, a, act, rhs, xp, par, i, one, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 0, false>(acc, a, act, rhs, xm, opar, xm, one, stride);
+        } else if (wv == 2) {
+            const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
+            const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
+            hop_dir<SP, GP, 1, NE, G5, LNT, 1, true>(acc, a, act, rhs, yp, par, i, one, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 1, false>(acc, a, act, rhs, ym, opar, ym, one, stride);
+        } else if (wv == 3) {
+            const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
+            const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
+            hop_dir<SP, GP, 1, NE, G5, LNT, 2, true>(acc, a, act, rhs, zp, par, i, one, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 2, false>(acc, a, act, rhs, zm, opar, zm, one, stride);
+        } else {
+            const int tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
+            const int tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+            const R sgn_tf = (NE == 6 && c.t == g.L[3] - 1) ? -one : one;
+            const R sgn_tb = (NE == 6 && c.t == 0) ? -one : one;
+            hop_dir<SP, GP, 1, NE, G5, LNT, 3, true>(acc, a, act, rhs, tp, par, i, sgn_tf, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 3, false>(acc, a, act, rhs, tm, opar, tm, sgn_tb, stride);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                part[wv - 1][2 * (s * 3 + k)][lane] = acc[0][s][k].re;
+                part[wv - 1][2 * (s * 3 + k) + 1][lane] = acc[0][s][k].im;
+            }
+    } else if (a.has_y) {  // z and w are loaded after the barrier (registers)
+        load_site<SP, R>(yv, a.y, stride, rhs, i);
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    Cx<R> acc[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int e = 2 * (s * 3 + k);
+            acc[s][k] = {((part[0][e][lane] + part[1][e][lane]) + part[2][e][lane]) + part[3][e][lane],
+                         ((part[0][e + 1][lane] + part[1][e + 1][lane]) + part[2][e + 1][lane]) + part[3][e + 1][lane]};
+        }
+    double red[3] = {0.0, 0.0, 0.0};
+    hop_finish<SP, CLV, 1>(a, i, valid, rhs, acc, yv, zv, wd, red);
+    const int nv = red_nvals(a.red);
+    if (nv == 0) return;
+    const int ntiles = (int)gridDim.x / a.nrhs;
+    const int ps = a.pstride ? a.pstride : ntiles;
+    double *dst = a.partials + (size_t)rhs * nv * ps + tile;
+    if (nv == 1) {
+        double v[1] = {red[0]};
+        wave_reduce_to<1>(v, dst, ps);
+    } else if (nv == 2) {
+        double v[2] = {red[0], red[1]};
+        wave_reduce_to<2>(v, dst, ps);
+    } else {
+        double v[3] = {red[0], red[1], red[2]};
+        wave_reduce_to<3>(v, dst, ps);
+    }
+}
+
+template <int SP, int GP, int NE, bool G5, bool LNT, bool CLV>
+static hipError_t launch_hop_ds(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    const dim3 grid(hop_nblocks(a, c) * a.nrhs), block(320);
+    hipLaunchKernelGGL((hop_kernel_ds<SP, GP, NE, G5, LNT, CLV>), grid, block, 0, s, a, c.xcd);
+    return hipGetLastError();
+}
+
 template <int SP, int GP, int NE, bool G5, bool LNT, bool SHX, bool CLV>
 static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const int ngroups = a.nrhs / c.rpt;
@@ -482,6 +593,11 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
 template <int SP, int GP, int NE, bool G5>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const bool lnt = a.nrhs == c.rpt;
+    if (c.dsplit) {
+        if (a.clov_mode != CLV_NONE)
+            return lnt ? launch_hop_ds<SP, GP, NE, G5, true, true>(a, c, s) : launch_hop_ds<SP, GP, NE, G5, false, true>(a, c, s);
+        return lnt ? launch_hop_ds<SP, GP, NE, G5, true, false>(a, c, s) : launch_hop_ds<SP, GP, NE, G5, false, false>(a, c, s);
+    }
     if (a.clov_mode != CLV_NONE)  // clover epilogue: its own instantiations (one RHS per lane)
         return lnt ? launch_hop_k<SP, GP, NE, G5, true, false, true>(a, c, s)
                    : launch_hop_k<SP, GP, NE, G5, false, false, true>(a, c, s);

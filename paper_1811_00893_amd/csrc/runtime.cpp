@@ -153,7 +153,8 @@ TuneTable &tune_table() {
         T->path = path;
         std::ifstream in(T->path);
         std::string line;
-        // one JSON object per line: {"key": "...", "block": B, "rpt": R, "xcd": X, "zblk": Z, "lds_kb": K, "wsplit": W, "ms": T}
+        // one JSON object per line: {"key": "...", "block": B, "rpt": R, "xcd": X, "zblk": Z, "lds_kb": K,
+        // "wsplit": W, "shx": S, "dsplit": D, "ms": T}
         while (std::getline(in, line)) {
             const size_t k0 = line.find("\"key\": \"");
             if (k0 == std::string::npos) continue;
@@ -163,8 +164,8 @@ TuneTable &tune_table() {
             wl::LaunchCfg c;
             if (std::sscanf(line.c_str() + k1,
                             "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d, "
-                            "\"shx\": %d",
-                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit, &c.shx) >= 5)
+                            "\"shx\": %d, \"dsplit\": %d",
+                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit, &c.shx, &c.dsplit) >= 5)
                 T->cfg[key] = c;
         }
         return T;
@@ -177,7 +178,7 @@ void TuneTable::save(const std::string &key, const wl::LaunchCfg &c, double ms) 
     std::ofstream out(path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
         << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"wsplit\": " << c.wsplit
-        << ", \"shx\": " << c.shx << ", \"ms\": " << ms << "}\n";
+        << ", \"shx\": " << c.shx << ", \"dsplit\": " << c.dsplit << ", \"ms\": " << ms << "}\n";
 }
 
 namespace wl {
@@ -201,6 +202,10 @@ static std::string hop_key(const HopArgs &a) {
 // then the plane blocking, the wave split and the block size fall back if they still do not fit.
 static LaunchCfg fit_cfg(const HopArgs &a, LaunchCfg c) {
     if (hop_cfg_valid(a, c)) return c;
+    if (c.dsplit) {  // the direction split's shape is fixed; otherwise the default block
+        c.dsplit = 0;
+        c.block = 256;
+    }
     if (a.clov_mode != CLV_NONE) {
         c.rpt = 1;
         c.shx = 0;
@@ -213,10 +218,18 @@ static LaunchCfg fit_cfg(const HopArgs &a, LaunchCfg c) {
     return c;
 }
 
+// Lattices below 4096 sites per parity are not tuned: they take the direction split (the
+// plain kernel would run a few dozen waves, each a chain of dependent gathers).
 static LaunchCfg default_cfg(const HopArgs &a) {
     LaunchCfg c;
-    c.block = 256;
     c.xcd = 1;
+    if (a.g.Vh < 4096) {
+        c.block = 320;
+        c.dsplit = 1;
+        if (hop_cfg_valid(a, c)) return c;
+        c.dsplit = 0;
+    }
+    c.block = 256;
     const int maxr = a.in.prec == P64 ? 2 : 4;
     for (int r = maxr; r >= 1; r--)
         if (a.nrhs % r == 0) { c.rpt = r; break; }
@@ -251,6 +264,13 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
                             c.shx = shx;
                             if (hop_cfg_valid(a, c)) cands.push_back(c);
                         }
+    for (int xcd : {1, 0}) {  // the direction split (small lattices)
+        LaunchCfg c;
+        c.block = 320;
+        c.xcd = xcd;
+        c.dsplit = 1;
+        if (hop_cfg_valid(a, c)) cands.push_back(c);
+    }
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
@@ -270,8 +290,8 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         WL_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
         if (std::getenv("WILSON_TUNE_VERBOSE"))
-            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d shx=%d: %.2f us\n", hop_key(a).c_str(),
-                         c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, c.wsplit, c.shx, per * 1e3);
+            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d shx=%d ds=%d: %.2f us\n",
+                         hop_key(a).c_str(), c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, c.wsplit, c.shx, c.dsplit, per * 1e3);
         if (per < bms) {
             bms = per;
             best = c;
@@ -293,8 +313,8 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
         const char *fc = std::getenv("WILSON_HOP_CFG");
         if (fc) {
             LaunchCfg &c = ctx->forced_cfg;
-            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit,
-                                      &c.shx) >= 4;
+            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb,
+                                      &c.wsplit, &c.shx, &c.dsplit) >= 4;
         }
     }
     LaunchCfg cfg;

@@ -191,7 +191,7 @@ def test_clover_attach_rejects_bad_terms(L):
         close(L, ctx, g)
 
 
-@pytest.mark.parametrize("cfg", ["64,2,1,4", "128,1,1,0,0,1", "256,1,0,0,40,0,1"])
+@pytest.mark.parametrize("cfg", ["64,2,1,4", "128,1,1,0,0,1", "256,1,0,0,40,0,1", "320,1,1,0,0,0,0,1"])
 def test_clover_every_launch_config(L, cfg, monkeypatch):
     """Pinned launch configurations are fitted to the clover kernels (one RHS per lane,
     no lane exchange) and give the oracle's D_clov."""

@@ -219,11 +219,12 @@ def test_batched_point_sources(L, ctx):
     L.wilson_gauge_free(ctx, g)
 
 
-@pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1"])
+@pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1", "320,1,1,0,0,0,0,1"])
 def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
     """The batched solve with the hop's RHS groups split over the waves of a block (each
-    wave writes its own partial sums of the fused reductions) converges for every RHS
-    to the oracle's residual test and agrees with the default configuration."""
+    wave writes its own partial sums of the fused reductions), or with each block's
+    directions split over its waves, converges for every RHS to the oracle's residual
+    test and agrees with the default configuration."""
     dims = (4, 4, 8, 8)  # Vh = 512: eight 64-site tiles
     k, tol = 0.125, 1e-10
     U = inputs.gauge_field(dims, eps=0.3, seed=1005)
@@ -253,11 +254,12 @@ def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
             L.wilson_context_destroy(c)
 
 
-@pytest.mark.parametrize("cfg", ["256,1,1,0,0,0,1", "64,1,1,4,0,0,1"])
+@pytest.mark.parametrize("cfg", ["256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1"])
 def test_solves_with_lane_exchange(L, cfg, monkeypatch):
-    """Solves whose hops take x/y neighbours from other lanes: BiCGStab and CGNR (gamma5
-    on the hop input and output) in FP64, and mixed precision with FP16 spinors, all to
-    the oracle's residual test."""
+    """Solves whose hops take x/y neighbours from other lanes, or split the eight
+    directions over the waves of a block: BiCGStab and CGNR (gamma5 on the hop input and
+    output) in FP64, and mixed precision with FP16 spinors, all to the oracle's residual
+    test."""
     monkeypatch.setenv("WILSON_HOP_CFG", cfg)
     dims = (8, 8, 8, 8)
     k, tol = 0.125, 1e-10
@@ -337,11 +339,13 @@ def test_full_size_sampled_dslash(L, ctx):
 
 @pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2",
                                  "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1",
-                                 "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,1,1,0,0,1,1", "256,1,1,2,0,0,1"])
+                                 "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,1,1,0,0,1,1", "256,1,1,2,0,0,1",
+                                 "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
     XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
-    waves of a block, x/y neighbours exchanged between lanes) gives the oracle's result;
+    waves of a block, x/y neighbours exchanged between lanes, directions split over the
+    waves of a block) gives the oracle's result;
     the lattice has a ragged last block for every block size, rows of 3 sites (x wraps
     inside most wavefronts) and, with plane blocking, wavefronts whose sites are not
     contiguous."""
@@ -362,3 +366,26 @@ def test_dslash_every_launch_config(L, cfg, monkeypatch):
     finally:
         L.wilson_gauge_free(c, g)
         L.wilson_context_destroy(c)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_solve_bitwise_reproducible(L, ctx, prec):
+    """Reductions are summed in a fixed order on the device, so repeating a solve (after a
+    first one has settled the tuned launch shapes) gives the same bits."""
+    dims = (8, 4, 8, 8)
+    U, b = setup_case(dims, 60)
+    g = L.wilson_gauge_load(ctx, U.to(DEV), dims, L.WILSON_GAUGE_FP32 | L.WILSON_GAUGE_FP16)
+    try:
+        nrhs = 2
+        bb = inputs.gaussian_source(dims, seed=2060, nrhs=nrhs).to(DEV)
+        opts = {"precision": prec, "maxiter": 20000}
+        xs, its = [], []
+        for _ in range(3):
+            x = torch.zeros_like(bb)
+            st, info = L.wilson_solve_ex(ctx, g, x, bb, nrhs, [0.12, 0.125], [1e-10, 1e-11], opts)
+            assert st == 0, L.wilson_last_error()
+            xs.append(x.cpu())
+            its.append([d["iterations"] for d in info])
+        assert torch.equal(xs[1], xs[2]) and its[1] == its[2]
+    finally:
+        L.wilson_gauge_free(ctx, g)
