@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--outstanding", type=int, default=24, help="serving: requests in flight in the capacity run")
     p.add_argument("--step-iters", type=int, default=32, help="serving: most iterations per scheduler turn")
     p.add_argument("--turn-ms", type=float, default=3.0, help="serving: target duration of a scheduler turn")
+    p.add_argument("--max-heavy", type=int, default=2,
+                   help="serving: heavy batches (an iteration >= 0.5 ms) advancing at once, oldest first (0: no limit)")
     p.add_argument("--hbm-budget", type=float, default=200e9, help="serving: device bytes for fields + batches")
     return p.parse_args()
 
@@ -215,7 +217,7 @@ def run_serving(args):
 
     # the continuous-batching server
     sch, eng = make_server(hbm_budget=args.hbm_budget, nslots=12, step_iters=args.step_iters, precision=1,
-                           turn_ms=args.turn_ms)
+                           turn_ms=args.turn_ms, max_heavy=args.max_heavy if args.max_heavy > 0 else None)
     for gid, (d, e, s) in pool.items():
         sch.register_gauge(gid, d, eng.load_gauge(gid, U[gid], d))
     eng.alloc_solution = lambda req: torch.zeros_like(req.b)
@@ -305,7 +307,7 @@ def run_serving(args):
         "load_points": points,
         "rejected": len(sch.rejected),
         "config": {"lattices": sizes, "gauge_fields_per_size": 2, "nslots": 12, "step_iters_max": args.step_iters,
-                   "turn_ms": args.turn_ms,
+                   "turn_ms": args.turn_ms, "max_heavy": args.max_heavy,
                    "precision": "mixed_fp32", "latency": "arrival to solution in device memory",
                    "loads_relative_to": "closed-loop capacity of the continuous-batching server"},
     }

@@ -59,13 +59,19 @@ class Scheduler:
     """Admission, slot assignment, stepping and retirement (engine-agnostic)."""
 
     def __init__(self, engine, hbm_budget: float, nslots: int = 12, step_iters: int = 8, clock=time.perf_counter,
-                 turn_ms: Optional[float] = None):
+                 turn_ms: Optional[float] = None, max_heavy: Optional[int] = None, heavy_ms: float = 0.5):
         self.engine = engine
         self.budget = float(hbm_budget)
         self.nslots = nslots
         self.step_iters = step_iters   # iterations per turn (the maximum when turn_ms is set)
         self.turn_ms = turn_ms         # target wall time of a turn: iterations adapt to it
         self.iters = step_iters
+        # at most `max_heavy` heavy batches (an iteration estimated at >= heavy_ms) advance
+        # at once, those holding the oldest requests first (None: no limit)
+        if max_heavy is not None and max_heavy < 1:
+            raise ValueError("max_heavy must be >= 1 (or None)")
+        self.max_heavy = max_heavy
+        self.heavy_ms = heavy_ms
         self.clock = clock
         self.gauges: Dict[Any, dict] = {}      # gauge_id -> {"dims", "bytes"}
         self.batches: Dict[Any, dict] = {}     # gauge_id -> {"handle", "slots": [(req, k) | None], "bytes"}
@@ -150,20 +156,42 @@ class Scheduler:
             return int(min(self.step_iters, max(1, round(self.turn_ms / max(ms, 1e-3)))))
         return self.iters
 
+    def _heavy(self, b):
+        est = getattr(self.engine, "iter_ms", None)
+        if est is None:
+            return False
+        return est(b["handle"], sum(s is not None for s in b["slots"])) >= self.heavy_ms
+
+    def _may_advance(self, active):
+        """Batches that may start a turn now.  Heavy batches share the GPU's bandwidth:
+        several at once each run slower, and the requests that then finish last are the
+        large ones that waited longest.  With `max_heavy`, only that many heavy batches
+        advance, ordered by the arrival of their oldest request (the others keep their
+        slots and wait); light batches always advance."""
+        if self.max_heavy is None:
+            return active
+        heavy = [b for b in active if self._heavy(b)]
+        heavy.sort(key=lambda b: min(s[0].arrival for s in b["slots"] if s is not None))
+        held = set(id(b) for b in heavy[self.max_heavy:])
+        return [b for b in active if id(b) not in held]
+
     def step(self):
         """One pass of the loop: start a turn on every batch with running slots that has
-        none in flight, then retire the slots of every batch whose turn has finished.  With
-        an engine that can tell whether a batch's turn is done (`ready`) the batches run
-        their turns independently (a small lattice does not wait for a large one's turn);
-        otherwise every started turn is waited for in this pass."""
+        none in flight (within the heavy-batch limit), then retire the slots of every batch
+        whose turn has finished.  With an engine that can tell whether a batch's turn is
+        done (`ready`) the batches run their turns independently (a small lattice does not
+        wait for a large one's turn); otherwise every started turn is waited for in this
+        pass."""
         active = [b for b in self.batches.values() if any(s is not None for s in b["slots"])]
         t0 = time.perf_counter()
         ready = getattr(self.engine, "ready", None)
-        for b in active:                       # enqueue on every idle stream first ...
+        for b in self._may_advance(active):    # enqueue on every idle stream first ...
             if not b.get("inflight"):
                 self.engine.step(b["handle"], self._iters_for(b))
                 b["inflight"] = True
         for b in active:                       # ... then retire what has finished
+            if not b.get("inflight"):
+                continue
             if ready is not None and not ready(b["handle"]):
                 continue
             b["inflight"] = False
@@ -288,6 +316,7 @@ class LibEngine:
         self.gauge.clear()
 
 
-def make_server(hbm_budget, nslots=12, step_iters=8, precision=1, solver=0, turn_ms=None):
+def make_server(hbm_budget, nslots=12, step_iters=8, precision=1, solver=0, turn_ms=None, max_heavy=None):
     eng = LibEngine(precision=precision, solver=solver)
-    return Scheduler(eng, hbm_budget, nslots=nslots, step_iters=step_iters, turn_ms=turn_ms), eng
+    return Scheduler(eng, hbm_budget, nslots=nslots, step_iters=step_iters, turn_ms=turn_ms,
+                     max_heavy=max_heavy), eng

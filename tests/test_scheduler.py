@@ -228,3 +228,41 @@ def test_independent_turns_with_ready():
     assert sorted(r.rid for r in sch.completed) == [0, 1, 2]
     assert all(not b.get("inflight") for b in sch.batches.values())
     assert eng.steps > steps_before
+
+
+def test_heavy_batches_take_turns_oldest_first():
+    """With max_heavy = 1 only the heavy batch holding the oldest request advances; the
+    other heavy batch keeps its slots and waits, light batches advance meanwhile, and the
+    waiting batch runs once the first drains."""
+    class CostEngine(FakeEngine):
+        cost = {"big1": 3.0, "big2": 3.0, "small": 0.05}
+
+        def __init__(self):
+            super().__init__()
+            self.log = []
+
+        def iter_ms(self, h, n_active):
+            return self.cost[h[0]]
+
+        def step(self, h, iters):
+            self.log.append(h[0])
+            super().step(h, iters)
+
+    eng = CostEngine()
+    sch = Scheduler(eng, hbm_budget=1e9, nslots=2, step_iters=4, clock=Clock(), max_heavy=1, heavy_ms=1.0)
+    for gid in ("big2", "big1", "small"):
+        sch.register_gauge(gid, (4, 4, 4, 4), 1)
+    sch.submit(mkreq(0, "big1", 1, kappa=0.02))   # oldest: 20 iterations
+    sch.submit(mkreq(1, "big2", 1, kappa=0.02))
+    sch.submit(mkreq(2, "small", 1, kappa=0.01))
+    sch.admit()
+    sch.step()
+    assert sorted(eng.log) == ["big1", "small"]
+    while not any(r.rid == 0 for r in sch.completed):
+        sch.admit()
+        sch.step()
+    assert "big2" not in eng.log                 # held until the oldest heavy request finished
+    sch.run_until_idle()
+    assert sorted(r.rid for r in sch.completed) == [0, 1, 2]
+    with pytest.raises(ValueError):
+        Scheduler(eng, hbm_budget=1e9, max_heavy=0)
