@@ -11,7 +11,12 @@ hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
 // ---------------------------------------------------------------------------------
 bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
     if (c.dsplit)  // one RHS per block, five waves, memory-order tiles of 64 sites
-        return c.dsplit == 1 && c.block == 320 && c.rpt == 1 && !c.shx && !c.wsplit && c.zblk == 0 && c.lds_kb == 0;
+        return c.dsplit == 1 && c.block == 320 && c.rpt == 1 && !c.shx && !c.wsplit && c.zblk == 0 && c.lds_kb == 0 &&
+               !c.ldsl;
+    if (c.ldsl) {  // links in LDS: wave split, one or two RHS per lane, no clover epilogue
+        if (c.ldsl != 1 || !c.wsplit || c.lds_kb != 0 || c.rpt > 2 || (c.shx && c.rpt != 1)) return false;
+        if (a.clov_mode != CLV_NONE || (a.gprec == P64 && a.recon == 18)) return false;
+    }
     if (c.rpt < 1 || c.rpt > 4) return false;
     if (c.shx && c.rpt != 1) return false;  // with more RHS per lane the exchange spills
     if (a.clov_mode != CLV_NONE && (c.rpt != 1 || c.shx)) return false;  // clover kernels: one RHS per lane

@@ -110,21 +110,30 @@ __device__ __forceinline__ void proj_in(const Cx<real_t<SP>> (&comp)[12], real_t
 }
 
 // SRC selects where the neighbour comes from: 0 = loaded here from the input field;
-// 1 = its projected half spinors given in H.
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD, int SRC = 0>
+// 1 = its projected half spinors given in H.  LL: the link comes from the block's LDS copy
+// `ll` (see stage_links) instead of global memory.
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD, int SRC = 0, bool LL = false>
 __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
                                         int r0, int nbr, int link_par, int link_site, real_t<SP> sgn, int stride,
-                                        const Cx<real_t<SP>> (*H)[2][3] = nullptr) {
+                                        const Cx<real_t<SP>> (*H)[2][3] = nullptr, const char *ll = nullptr) {
     using R = real_t<SP>;
     // link U_mu(x) (forward, at the output site) or U_mu(x - mu) (backward, at the neighbour)
     Cx<R> U[3][3];
     {
         constexpr int NL = LinkElems<GP, NE>::N, CPL = LinkPack<GP>::CPL;
         Cx<R> ue[NL * CPL];
-        const unsigned loff = (unsigned)link_site * LinkPack<GP>::EB;
+        if constexpr (LL) {
+            constexpr int d = 2 * MU + (FWD ? 0 : 1);
+            const unsigned lane = threadIdx.x & 63u;
 #pragma unroll
-        for (int e = 0; e < NL; e++)
-            ld_link_elem<GP, R, LNT>(&ue[e * CPL], lplane<GP>(a.gauge, (link_par * 4 + MU) * NL + e, stride), loff);
+            for (int e = 0; e < NL; e++)
+                ld_link_elem<GP, R, false>(&ue[e * CPL], ll, ((unsigned)(d * NL + e) * 64u + lane) * LinkPack<GP>::EB);
+        } else {
+            const unsigned loff = (unsigned)link_site * LinkPack<GP>::EB;
+#pragma unroll
+            for (int e = 0; e < NL; e++)
+                ld_link_elem<GP, R, LNT>(&ue[e * CPL], lplane<GP>(a.gauge, (link_par * 4 + MU) * NL + e, stride), loff);
+        }
 #pragma unroll
         for (int e = 0; e < NE; e++) U[e / 3][e % 3] = ue[e];
     }
@@ -311,7 +320,30 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
     }
 }
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV>
+// With the wave split all waves of a block work on the same 64 sites, so each link of the
+// tile is needed by every wave: the waves load it once into LDS, wave w the directions
+// d = w, w + nw, ... (lane l for site l of the tile), and everyone reads it from there.
+// Every wave of the block calls this (it holds a block barrier).
+template <int GP, int NE>
+__device__ __forceinline__ void stage_links(char *ll, const HopArgs &a, int par, const int (&lsite)[8]) {
+    constexpr int NL = LinkElems<GP, NE>::N;
+    constexpr unsigned EB = LinkPack<GP>::EB;
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
+    for (int d = w; d < 8; d += nw) {
+        const int mu = d >> 1, lpar = (d & 1) ? 1 - par : par;
+        const int site = lsite[d];
+#pragma unroll
+        for (int e = 0; e < NL; e++) {
+            const char *src = lplane<GP>(a.gauge, (lpar * 4 + mu) * NL + e, a.g.stride) + (unsigned)site * EB;
+            char *dst = ll + ((unsigned)(d * NL + e) * 64u + lane) * EB;
+            if constexpr (EB == 16) *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+            else *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+        }
+    }
+    __syncthreads();
+}
+
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV, bool LL = false>
 __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, int r0, const bool (&act)[RPT],
                                          double (&red)[RPT][3]) {
     using R = real_t<SP>;
@@ -328,6 +360,18 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
     const int tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
     const int tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+
+    const char *ll = nullptr;
+    if constexpr (LL) {
+        __shared__ __align__(16) char ll_buf[8 * LinkElems<GP, NE>::N * 64 * LinkPack<GP>::EB];
+        const int lsite[8] = {i, xm, i, ym, i, zm, i, tm};
+        stage_links<GP, NE>(ll_buf, a, par, lsite);
+        ll = ll_buf;
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < RPT; r++) any |= act[r];
+        if (!any) return;  // after the barrier: this wave's RHS group has finished
+    }
 
     Cx<R> acc[RPT][4][3];
 #pragma unroll
@@ -348,23 +392,23 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
         load_raw<SP, RPT>(C, Cs, a, act, r0, i, stride);
         Cx<R> H[RPT][2][3];
         lane_nbr<SP, RPT, 0, true, G5>(H, C, Cs, a, act, r0, i, xp, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 1>(acc, a, act, r0, xp, par, i, one, stride, H);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 1, LL>(acc, a, act, r0, xp, par, i, one, stride, H, ll);
         lane_nbr<SP, RPT, 0, false, G5>(H, C, Cs, a, act, r0, i, xm, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 1>(acc, a, act, r0, xm, opar, xm, one, stride, H);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 1, LL>(acc, a, act, r0, xm, opar, xm, one, stride, H, ll);
         lane_nbr<SP, RPT, 1, true, G5>(H, C, Cs, a, act, r0, i, yp, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 1>(acc, a, act, r0, yp, par, i, one, stride, H);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 1, LL>(acc, a, act, r0, yp, par, i, one, stride, H, ll);
         lane_nbr<SP, RPT, 1, false, G5>(H, C, Cs, a, act, r0, i, ym, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 1>(acc, a, act, r0, ym, opar, ym, one, stride, H);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 1, LL>(acc, a, act, r0, ym, opar, ym, one, stride, H, ll);
     } else {
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true>(acc, a, act, r0, xp, par, i, one, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false>(acc, a, act, r0, xm, opar, xm, one, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true>(acc, a, act, r0, yp, par, i, one, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false>(acc, a, act, r0, ym, opar, ym, one, stride);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 0, LL>(acc, a, act, r0, xp, par, i, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 0, LL>(acc, a, act, r0, xm, opar, xm, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 0, LL>(acc, a, act, r0, yp, par, i, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 0, LL>(acc, a, act, r0, ym, opar, ym, one, stride, nullptr, ll);
     }
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true>(acc, a, act, r0, zp, par, i, one, stride);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false>(acc, a, act, r0, zm, opar, zm, one, stride);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true>(acc, a, act, r0, tp, par, i, sgn_tf, stride);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true, 0, LL>(acc, a, act, r0, zp, par, i, one, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false, 0, LL>(acc, a, act, r0, zm, opar, zm, one, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true, 0, LL>(acc, a, act, r0, tp, par, i, sgn_tf, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false, 0, LL>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride, nullptr, ll);
 
 #pragma unroll
     for (int r = 0; r < RPT; r++) {
@@ -391,7 +435,7 @@ struct HopOcc {
     static constexpr int value = SP == P64 ? 2 : (RPT <= 2 ? 4 : 3);
 };
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV>
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV, bool LL = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<SP, RPT>::value)))
 hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     const Geom &g = a.g;
@@ -415,7 +459,9 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
         act[r] = (r0 + r < a.nrhs) && (a.state == nullptr || (a.state[r0 + r].phase & a.run_mask));
         any |= act[r];
     }
-    if (!any) return;  // uniform over the block (over the wave with wsplit)
+    // uniform over the block (over the wave with wsplit); with the links in LDS every wave
+    // takes part in loading them first
+    if (!any && !LL) return;
 
     double red[RPT][3];
 #pragma unroll
@@ -423,7 +469,8 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
 
     const bool valid = l < g.Vh;
     const int i = valid ? visit_order(l, g, vo) : g.Vh - 1;
-    hop_site<SP, GP, RPT, NE, G5, LNT, SHX, CLV>(a, i, valid, r0, act, red);
+    hop_site<SP, GP, RPT, NE, G5, LNT, SHX, CLV, LL>(a, i, valid, r0, act, red);
+    if (LL && !any) return;
 
     const int nv = red_nvals(a.red);
     if (nv == 0) return;
@@ -588,11 +635,37 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
     return hipGetLastError();
 }
 
+// Wave split with the tile's links staged in LDS (one or two RHS per lane, no clover
+// epilogue; links through L2 since several RHS groups read them).
+template <int SP, int GP, int NE, bool G5, bool SHX>
+static hipError_t launch_hop_ll(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    const int ngroups = a.nrhs / c.rpt;
+    const dim3 grid(hop_nblocks(a, c) * (ngroups / (c.block / 64))), block(c.block);
+    VisitOrder vo;
+    if (c.zblk > 0) {
+        vo.zblk = c.zblk;
+        vo.plane = make_fastdiv((uint32_t)(a.g.Lxh * a.g.L[1]));
+        vo.per_zb = make_fastdiv((uint32_t)(c.zblk * a.g.L[3]));
+        vo.zb = make_fastdiv((uint32_t)c.zblk);
+    }
+    if (c.rpt == 1)
+        hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, false, SHX, false, true>), grid, block, 0, s, a, c.xcd, vo, 1);
+    else if (c.rpt == 2 && !SHX)
+        hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, false, false, false, true>), grid, block, 0, s, a, c.xcd, vo, 1);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // Links are loaded non-temporally when one group covers every right-hand side (each link
 // is read once per launch) and through L2 otherwise.
 template <int SP, int GP, int NE, bool G5>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const bool lnt = a.nrhs == c.rpt;
+    if (c.ldsl) {
+        if constexpr (GP == P64 && NE == 9) return hipErrorInvalidValue;  // 72 KB of links per tile
+        else return c.shx ? launch_hop_ll<SP, GP, NE, G5, true>(a, c, s) : launch_hop_ll<SP, GP, NE, G5, false>(a, c, s);
+    }
     if (c.dsplit) {
         if (a.clov_mode != CLV_NONE)
             return lnt ? launch_hop_ds<SP, GP, NE, G5, true, true>(a, c, s) : launch_hop_ds<SP, GP, NE, G5, false, true>(a, c, s);

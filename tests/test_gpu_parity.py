@@ -219,12 +219,14 @@ def test_batched_point_sources(L, ctx):
     L.wilson_gauge_free(ctx, g)
 
 
-@pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1", "320,1,1,0,0,0,0,1"])
+@pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1", "320,1,1,0,0,0,0,1",
+                                 "256,1,1,4,0,1,1,0,1", "128,2,1,0,0,1,0,0,1"])
 def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
     """The batched solve with the hop's RHS groups split over the waves of a block (each
-    wave writes its own partial sums of the fused reductions), or with each block's
-    directions split over its waves, converges for every RHS to the oracle's residual
-    test and agrees with the default configuration."""
+    wave writes its own partial sums of the fused reductions; also with the tile's links
+    staged in LDS once for all waves), or with each block's directions split over its
+    waves, converges for every RHS to the oracle's residual test and agrees with the
+    default configuration."""
     dims = (4, 4, 8, 8)  # Vh = 512: eight 64-site tiles
     k, tol = 0.125, 1e-10
     U = inputs.gauge_field(dims, eps=0.3, seed=1005)
@@ -340,12 +342,14 @@ def test_full_size_sampled_dslash(L, ctx):
 @pytest.mark.parametrize("cfg", ["64,1,0,0", "128,1,1,0", "256,1,1,2", "64,1,1,4", "128,2,1,2", "64,4,1,2",
                                  "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1",
                                  "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,1,1,0,0,1,1", "256,1,1,2,0,0,1",
-                                 "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1"])
+                                 "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1", "256,1,1,0,0,1,1,0,1",
+                                 "128,2,1,2,0,1,0,0,1"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
     XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
-    waves of a block, x/y neighbours exchanged between lanes, directions split over the
-    waves of a block) gives the oracle's result;
+    waves of a block (with or without the tile's links staged in LDS), x/y neighbours
+    exchanged between lanes, directions split over the waves of a block) gives the
+    oracle's result;
     the lattice has a ragged last block for every block size, rows of 3 sites (x wraps
     inside most wavefronts) and, with plane blocking, wavefronts whose sites are not
     contiguous."""
