@@ -225,8 +225,8 @@ def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
     """The batched solve with the hop's RHS groups split over the waves of a block (each
     wave writes its own partial sums of the fused reductions; also with the tile's links
     staged in LDS once for all waves), or with each block's directions split over its
-    waves, converges for every RHS to the oracle's residual test and agrees with the
-    default configuration."""
+    waves, converges for every RHS to the oracle's residual test (BiCGStab in FP64, FP32
+    and with FP16 spinors, CGNR in FP64) and agrees with the default configuration."""
     dims = (4, 4, 8, 8)  # Vh = 512: eight 64-site tiles
     k, tol = 0.125, 1e-10
     U = inputs.gauge_field(dims, eps=0.3, seed=1005)
@@ -238,19 +238,21 @@ def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
         c = L.wilson_context_create()
         g = L.wilson_gauge_load(c, U.to(DEV), dims, L.WILSON_GAUGE_FP32)
         try:
-            for prec in (0, 1):
+            # BiCGStab in FP64 and FP32, CGNR (gamma5 on the hops) in FP64, FP16 spinors
+            for solver, prec in ((0, 0), (0, 1), (1, 0), (0, 3)):
                 x = torch.zeros_like(b, device=DEV)
-                st, _ = L.wilson_solve_ex(c, g, x, b.to(DEV), 12, [k] * 12, [tol] * 12, {"precision": prec})
-                assert st == 0, (cfg, prec, st, L.wilson_last_error())
+                st, _ = L.wilson_solve_ex(c, g, x, b.to(DEV), 12, [k] * 12, [tol] * 12,
+                                          {"precision": prec, "solver": solver, "maxiter": 20000})
+                assert st == 0, (cfg, solver, prec, st, L.wilson_last_error())
                 xs = x.cpu().numpy()
                 if not forced:
-                    ref[prec] = xs
+                    ref[solver, prec] = xs
                     continue
                 for j in range(12):
-                    assert oracle_residual(xs[j], b[j].numpy(), U.numpy(), k, dims) < tol, (cfg, prec, j)
-                d = rel(xs, ref[prec])
-                print(f"{cfg} prec {prec}: wave-split vs default {d:.2e}")
-                assert d < 1e-8
+                    assert oracle_residual(xs[j], b[j].numpy(), U.numpy(), k, dims) < tol, (cfg, solver, prec, j)
+                d = rel(xs, ref[solver, prec])
+                print(f"{cfg} solver {solver} prec {prec}: vs default {d:.2e}")
+                assert d < 1e-7
         finally:
             L.wilson_gauge_free(c, g)
             L.wilson_context_destroy(c)
