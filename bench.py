@@ -391,11 +391,14 @@ def run_layouts(args):
     }
 
 
-def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None):
+def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check=None):
     """The FP64 oracle timed on the host: an even-odd BiCGStab solve (run for 1 and 1+k
     iterations, whose difference isolates the cost of an iteration, scaled to the number
     of iterations the GPU solve took), and the operator units (parity hop, full D) with
-    all threads and the parity hop on one thread."""
+    all threads and the parity hop on one thread.  With `check` (GPU results copied to the
+    host: a solution x of right-hand side xb, and an operator output dout of input din with
+    its parity dpar), the oracle's FP64 operator also grades them: |xb - D x| / |xb| and
+    |dout - oracle| / |oracle| (outside the timed region)."""
     import numpy as np
 
     import oracle
@@ -440,6 +443,21 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None):
     finally:
         oracle.set_threads(nthr)
     triad = oracle.triad_gbps()
+    graded = None
+    if check is not None:
+        xr, xbr, dout, din, dpar = check
+        if Fn is None:
+            dx = oracle.apply_D(xr, Un, kappa, dims)
+            dref = oracle.dslash(din, Un, kappa, dims, dpar) if dpar < 2 else oracle.apply_D(din, Un, kappa, dims)
+        else:
+            dx = oracle.apply_Dclov(xr, Un, Fn, kappa, dims)
+            dref = oracle.apply_Dclov(din, Un, Fn, kappa, dims)
+        graded = {
+            "solution_residual_by_oracle": float(np.linalg.norm(xbr - dx) / np.linalg.norm(xbr)),
+            "operator_rel_error_vs_oracle": float(np.linalg.norm(dout - dref) / np.linalg.norm(dref)),
+            "operator": ("D_clov" if Fn is not None else ("parity hop" if dpar < 2 else "D")) +
+                        f" in the workload's precision ({['fp64', 'fp32', 'fp16', 'fp16 spinors + fp32 links'][precision]})",
+        }
     what = ("the same right-hand side" if nrhs == 1 else
             f"right-hand side 0 of the {nrhs}, the batch costed as {nrhs} sequential solves")
     inner = "" if precision == 0 else " (the GPU's inner iterations in reduced precision; the oracle is FP64)"
@@ -462,6 +480,7 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None):
             "full_d_gflops": (counts.FULL_D_FLOPS_PER_SITE if Fn is None else counts.CLOVER_FLOPS_PER_SITE) * V / d_s / 1e9,
             "host_triad_gbs": triad,
         },
+        "gpu_results_graded_by_oracle": graded,
     }
 
 
@@ -625,6 +644,8 @@ def main():
         res.append(max(d["true_residual"] for d in info))
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    # the last timed solution, kept for the oracle's grading (later solves reuse x)
+    x_last = (x[0] if nrhs > 1 else x).cpu().numpy()
     # per-kernel figures from a separate pass with event timing on (event records around
     # every launch would slow the launch-bound small lattices in the timed region)
     n_prof = min(args.steps, 3)
@@ -705,7 +726,17 @@ def main():
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)), F)
+        # the last timed solution and one operator application, graded by the oracle
+        j = args.warmup + args.steps - 1
+        xr = x_last
+        xbr = (srcs[j][0] if nrhs > 1 else srcs[j]).cpu().numpy()
+        din = xbr
+        dout_t = torch.zeros_like(srcs[j][0] if nrhs > 1 else srcs[j])
+        L.check(L.wilson_dslash_ex(ctx, g, dout_t, srcs[j][0].contiguous() if nrhs > 1 else srcs[j], kappa, dpar,
+                                   dprec, 1), "graded dslash")
+        dout = dout_t.cpu().numpy()
+        cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)), F,
+                           check=(xr, xbr, dout, din, dpar))
 
     line = {
         "metric": METRIC,

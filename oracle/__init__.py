@@ -311,3 +311,7 @@ def num_threads():
 def set_threads(n):
     """OpenMP threads for later oracle calls (timing only)."""
     _load().oracle_set_threads(int(n))
+
+
+# block BiCGStab for several right-hand sides of one matrix (kept in its own module)
+from .block_krylov import BlockBreakdown, block_bicgstab, solve_block  # noqa: E402,F401
