@@ -79,7 +79,20 @@ typedef enum {
 
 typedef enum {
     WILSON_SOLVER_BICGSTAB_EO = 0, /* BiCGStab on M_ee = 1 - kappa^2 H_eo H_oe */
-    WILSON_SOLVER_CGNR_EO = 1      /* CG on M_ee^dag M_ee (CGLS form), M_ee^dag = g5 M_ee g5 */
+    WILSON_SOLVER_CGNR_EO = 1,     /* CG on M_ee^dag M_ee (CGLS form), M_ee^dag = g5 M_ee g5 */
+    WILSON_SOLVER_BLOCK_BICGSTAB_EO = 2
+    /* Block BiCGStab on M_ee (Guennouni, Jbilou and Sadok 2003; the paper's BiCGStab of
+       Sec. 2 with the s right-hand sides of one call sharing one Krylov space: alpha and
+       beta become s x s matrices solved against the shadow block R~ = R_0, omega is one
+       Frobenius ratio).  wilson_solve_ex only, FP64 only (precision WILSON_FP64,
+       mixed_update 0), every kappa[k] equal (one matrix).  The right-hand sides are taken
+       in blocks of up to 16 consecutive non-zero ones (a zero b_k gets x_k = 0 and is left
+       out); each block stops when every column meets its tol[k] on the iterated residual,
+       and is then checked in FP64 like the other solvers.  A block whose s x s matrix
+       R~^H V is singular to working precision (pivot below 1e-13 of its largest entry:
+       e.g. linearly dependent right-hand sides) restarts from its current solution with
+       one BiCGStab recurrence per right-hand side (counted in `restarts`).  info[k]
+       .iterations counts block iterations (plus those of such a restart). */
 } wilson_solver;
 
 typedef struct wilson_ctx wilson_ctx;

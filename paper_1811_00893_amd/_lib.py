@@ -30,7 +30,7 @@ WILSON_BUSY = -7
 
 WILSON_FP64, WILSON_FP32, WILSON_FP16, WILSON_FP16_L32 = 0, 1, 2, 3
 WILSON_GAUGE_FP64, WILSON_GAUGE_FP32, WILSON_GAUGE_FP16 = 1, 2, 4
-WILSON_SOLVER_BICGSTAB_EO, WILSON_SOLVER_CGNR_EO = 0, 1
+WILSON_SOLVER_BICGSTAB_EO, WILSON_SOLVER_CGNR_EO, WILSON_SOLVER_BLOCK_BICGSTAB_EO = 0, 1, 2
 WILSON_KERNEL_HOP, WILSON_KERNEL_BLAS = 0, 1
 WILSON_LAYOUT_SOA, WILSON_LAYOUT_AOS, WILSON_LAYOUT_AOSOA, WILSON_LAYOUT_VNODE = 0, 1, 2, 3
 

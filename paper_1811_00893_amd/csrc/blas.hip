@@ -356,6 +356,10 @@ __device__ void fin_op(RhsState *st, const double a0, const double a1, const dou
         st->iter += 1;
         if (!finite(a0)) fail(FAIL_NONFINITE);
         else if (a0 <= st->stop2) st->phase = PH_DONE;
+    } else if constexpr (OP == FIN_BLOCK_TS) {
+        st->omega_re = a0;
+        st->omega_im = a1;
+        st->aux = a2;
     } else if constexpr (OP == FIN_CG_BETA) {
         if (!finite(a0)) { fail(FAIL_NONFINITE); return; }
         if (st->zz == 0.0) { fail(FAIL_BREAKDOWN); return; }
@@ -385,6 +389,7 @@ hipError_t launch_finalize(int op, const double *partials, int nvals, int nblock
         FIN_CASE(FIN_CG_R)
         FIN_CASE(FIN_CG_BETA)
         FIN_CASE(FIN_ADD_AUX)
+        FIN_CASE(FIN_BLOCK_TS)
         default: return hipErrorInvalidValue;
     }
 #undef FIN_CASE

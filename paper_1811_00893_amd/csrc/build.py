@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libwilson.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["dslash.hip", "dslash_p64.hip", "dslash_p32.hip", "dslash_p16.hip", "dslash_p16l32.hip", "clover.hip", "blas.hip", "layout.hip", "layout_lab.hip", "runtime.cpp", "solver.cpp", "capi.cpp"]
+SOURCES = ["dslash.hip", "dslash_p64.hip", "dslash_p32.hip", "dslash_p16.hip", "dslash_p16l32.hip", "clover.hip", "blas.hip", "block.hip", "layout.hip", "layout_lab.hip", "runtime.cpp", "solver.cpp", "capi.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-I", HERE, "-I", os.path.join(ROOT, "include")]

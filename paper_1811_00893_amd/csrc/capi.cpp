@@ -139,7 +139,14 @@ static void check_solve_args(const double *kappa, const double *tol, int nrhs, c
         WL_CHECK_ARG(std::isfinite(tol[k]) && tol[k] > 0.0, "tol must be finite and > 0");
     }
     if (o) {
-        WL_CHECK_ARG(o->solver == WILSON_SOLVER_BICGSTAB_EO || o->solver == WILSON_SOLVER_CGNR_EO, "unknown solver");
+        WL_CHECK_ARG(o->solver == WILSON_SOLVER_BICGSTAB_EO || o->solver == WILSON_SOLVER_CGNR_EO ||
+                         o->solver == WILSON_SOLVER_BLOCK_BICGSTAB_EO,
+                     "unknown solver");
+        if (o->solver == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
+            WL_CHECK_ARG(o->precision == WILSON_FP64, "block BiCGStab runs in FP64 only");
+            for (int k = 1; k < nrhs; k++)
+                WL_CHECK_ARG(kappa[k] == kappa[0], "block BiCGStab needs one kappa for all right-hand sides");
+        }
         WL_CHECK_ARG(o->precision >= WILSON_FP64 && o->precision <= WILSON_FP16_L32, "unknown precision");
         WL_CHECK_ARG(o->maxiter > 0, "maxiter must be > 0");
         WL_CHECK_ARG(o->mixed_update == 0 || o->mixed_update == 1, "mixed_update must be 0 or 1");
@@ -402,6 +409,8 @@ int wilson_batch_create(wilson_ctx *ctx, const wilson_gauge *g, int32_t nslots, 
         double k = 0.1, t = 1e-10;
         check_solve_args(&k, &t, 1, opts);
         WL_CHECK_ARG(opts->mixed_update == 0, "batches use defect correction (mixed_update 0)");
+        WL_CHECK_ARG(opts->solver != WILSON_SOLVER_BLOCK_BICGSTAB_EO,
+                     "batches solve each slot on its own (no block solver)");
     }
     *batch = reinterpret_cast<wilson_batch *>(batch_create(ctx, g, nslots, params_from(opts, 10000)));
     return WILSON_OK;

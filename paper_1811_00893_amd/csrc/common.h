@@ -115,7 +115,8 @@ enum FinOp : int {
     FIN_CG_ALPHA,       // alpha = zz / |w|^2
     FIN_CG_R,           // r2 after the update; iteration count; convergence
     FIN_CG_BETA,        // beta = |z'|^2 / zz; zz = |z'|^2
-    FIN_ADD_AUX         // aux += value 0
+    FIN_ADD_AUX,        // aux += value 0
+    FIN_BLOCK_TS        // omega = <t,s> (values 0, 1), aux = |t|^2 (value 2), summed over the block later
 };
 
 // Arguments of one parity-hop launch:  out = cH[rhs] * (G5out? g5:1) H (G5in? g5:1) in
@@ -171,6 +172,46 @@ struct LaunchCfg {
     int dsplit = 0;    // 1: five waves per 64-site tile, wave 1 + mu on direction mu (block 320, RPT 1)
     int ldsl = 0;      // 1: with wsplit, the tile's links loaded once into LDS for all waves of the block
 };
+
+// ---- block BiCGStab (several right-hand sides of one matrix share one Krylov space) ----
+constexpr int kMaxBlock = 16;  // right-hand sides per block; larger sets are split into blocks
+// Device-resident s x s matrices of one block iteration (complex, row-major [i][j]).
+struct BlockState {
+    double gram[2 * kMaxBlock * kMaxBlock * 2];  // one or two Gram matrices R~^H Y of the last reduction
+    double lu[kMaxBlock * kMaxBlock * 2];        // LU factors of R~^H V (unit L below the diagonal)
+    double alpha[kMaxBlock * kMaxBlock * 2];
+    double beta[kMaxBlock * kMaxBlock * 2];
+    double omega[2];
+    int piv[kMaxBlock];                          // row exchanged with row k at step k
+};
+// Arguments of the block kernels (FP64 fields of s right-hand sides, parity-split planes).
+struct BlockArgs {
+    Geom g;
+    int s;
+    Spinor a, b, c, d, x;   // operand roles per kernel
+    double *partials;       // [value][nblk]
+    int nblk;               // partial row length (set by the launcher)
+    BlockState *bs;
+    RhsState *state;        // the s per-RHS states; all carry the block's phase
+    RhsState *mirror;       // optional host-mapped copy written by the check step
+};
+enum BlockSolveOp : int {
+    BS_INIT = 0,   // make the per-RHS phases after the initial norms one block phase
+    BS_ALPHA,      // LU of G0 = R~^H V (kept), alpha = G0^-1 G1 with G1 = R~^H R
+    BS_BETA,       // omega = sum <T_j,S_j> / sum |T_j|^2; beta = -G0^-1 (R~^H T)
+    BS_CHECK       // |R_j|^2 from the update's partials; iteration count; convergence of all
+};
+enum BlockUpdateOp : int {
+    BU_S = 0,   // S(a) = R(b) - V(c) alpha
+    BU_XR,      // X += P(a) alpha + omega S(b); R(c) = S - omega T(d); |R_j|^2 partials
+    BU_P        // P(a) = R(b) + (P - omega V(c)) beta
+};
+// Gram: G_p = A^H B_p (A = a, B_0 = b, B_1 = c when np = 2) reduced into bs->gram.
+hipError_t launch_block_gram(BlockArgs a, int np, hipStream_t s);
+hipError_t launch_block_solve(int op, BlockArgs a, hipStream_t s);
+hipError_t launch_block_update(int op, BlockArgs a, hipStream_t s);
+// partial sums the block kernels need (doubles)
+size_t block_partials_doubles(const Geom &g);
 
 // ---- kernel launchers (implemented in the .hip files) ----
 int hop_nblocks(const HopArgs &a, const LaunchCfg &c);

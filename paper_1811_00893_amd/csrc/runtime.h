@@ -174,6 +174,19 @@ namespace wl {
 int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes);
 // Launch a BLAS kernel (timed as class BLAS).
 void blas(wilson_ctx *ctx, int op, BlasArgs &a, double algorithmic_bytes);
+// Launch any kernel sequence through `launch` (returning hipError_t), timed as class cls.
+template <typename F>
+void timed_launch(wilson_ctx *ctx, int cls, double algorithmic_bytes, F &&launch) {
+    if (ctx->timing) {
+        hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
+        WL_HIP(hipEventRecord(e0, ctx->stream));
+        WL_HIP(launch());
+        WL_HIP(hipEventRecord(e1, ctx->stream));
+        ctx->pending.push_back({e0, e1, cls, algorithmic_bytes});
+    } else {
+        WL_HIP(launch());
+    }
+}
 // Size of a partials buffer (doubles) that any hop or BLAS launch on g with nrhs can use.
 size_t partials_doubles(const Geom &g, int nrhs);
 // Algorithmic bytes of one hop launch (per output site: 8 links + input + output (+ y, z, w)).

@@ -57,6 +57,7 @@ class EoCore {
     FieldBuf r64, tmp64;                     // FP64 outer residual (mixed only)
     FieldBuf r, rh, p, v, s, t, tmp, rf, xin; // inner Krylov fields
     DevBuf partials, st_in, st_out;
+    DevBuf bstate;  // block BiCGStab: the s x s matrices of the iteration
     PinnedBuf mirror, hinit, hread;
     hipEvent_t ring_ev[kRing] = {};
 
@@ -74,7 +75,12 @@ class EoCore {
         }
         r.make(P, g, n); rh.make(P, g, n); p.make(P, g, n); v.make(P, g, n); s.make(P, g, n); t.make(P, g, n);
         tmp.make(P, g, n);
-        partials.alloc(partials_doubles(g, n) * sizeof(double));
+        size_t npart = partials_doubles(g, n);
+        if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
+            npart = std::max(npart, block_partials_doubles(g));
+            bstate.alloc(sizeof(BlockState));
+        }
+        partials.alloc(npart * sizeof(double));
         st_in.alloc(sizeof(RhsState) * n);
         st_out.alloc(sizeof(RhsState) * n);
         mirror.alloc(sizeof(RhsState) * n * kRing);
@@ -98,7 +104,7 @@ class EoCore {
         size_t b = 0;
         for (const FieldBuf *f : {&b_e, &b_o, &x_e, &x_o, &bp, &r64, &tmp64, &r, &rh, &p, &v, &s, &t, &tmp, &rf, &xin})
             b += f->buf.size();
-        return b + partials.size() + st_in.size() + st_out.size();
+        return b + partials.size() + st_in.size() + st_out.size() + bstate.size();
     }
 
     Spinor V(Spinor f) const {
@@ -191,6 +197,28 @@ class EoCore {
         a.a = V(a.a); a.b = V(a.b); a.c = V(a.c); a.d = V(a.d); a.e = V(a.e); a.x = V(a.x);
         blas(ctx, op, a, bytes);
     }
+    // block BiCGStab kernels on the selected range (s = nk right-hand sides)
+    enum { BK_GRAM, BK_SOLVE, BK_UPDATE };
+    BlockArgs block_args(RhsState *st, RhsState *mir = nullptr) const {
+        BlockArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.g = g;
+        a.s = nk;
+        a.partials = part();
+        a.bs = bstate.as<BlockState>();
+        a.state = S(st);
+        a.mirror = mir ? mir + k0 : nullptr;
+        return a;
+    }
+    void run_block(int kind, int op, BlockArgs a, double bytes) {
+        a.a = V(a.a); a.b = V(a.b); a.c = V(a.c); a.d = V(a.d); a.x = V(a.x);
+        timed_launch(ctx, WILSON_KERNEL_BLAS, bytes, [&]() {
+            if (kind == BK_GRAM) return launch_block_gram(a, op, ctx->stream);
+            if (kind == BK_SOLVE) return launch_block_solve(op, a, ctx->stream);
+            return launch_block_update(op, a, ctx->stream);
+        });
+    }
+
     double vec_bytes(int prec, int nvec) const {
         return (double)nvec * g.Vh * nk * (24.0 * real_bytes(prec) + (prec == P16 ? 4.0 : 0.0));
     }
@@ -305,6 +333,22 @@ class EoCore {
             }
             finalize(FIN_BICG_INIT, 1, nb, sin(), PH_RUN);
             for (Spinor f : {p.f, v.f, t.f}) WL_HIP(launch_zero(V(f), g, nk, ctx->stream));
+        } else if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
+            // R = rhs - A X (or rhs), P = R, R~ = R with the column norms, then one phase
+            // for the whole block (it runs while any column misses its threshold)
+            BlasArgs a = blas_args(sin(), PH_RUN);
+            if (use_x0) {
+                apply_M(r.f, x, tmp.f, false, RED_NONE, none, sin(), PH_RUN, &rhs);
+            } else {
+                a.a = r.f; a.b = rhs;
+                run_blas(BL_COPY_NORM, a, vec_bytes(P, 2));
+            }
+            a.a = p.f; a.b = r.f;
+            run_blas(BL_COPY_NORM, a, vec_bytes(P, 2));
+            a.a = rh.f; a.b = r.f;
+            run_blas(BL_COPY_NORM, a, vec_bytes(P, 2));
+            finalize(FIN_BICG_INIT, 1, nb, sin(), PH_RUN);
+            run_block(BK_SOLVE, BS_INIT, block_args(sin()), 0.0);
         } else {
             // CGLS: r = rhs - M x, z = M^dag r, p = z
             if (use_x0) {
@@ -335,7 +379,9 @@ class EoCore {
             const bool poll_here = ((it + 1) % poll_every == 0) || it + 1 == maxiter;
             const int slot = enq % kRing;
             RhsState *mir = poll_here ? mirror_dev(slot) : nullptr;
-            if (method == WILSON_SOLVER_BICGSTAB_EO) bicg_iter(x, mir); else cg_iter(x, mir);
+            if (method == WILSON_SOLVER_BICGSTAB_EO) bicg_iter(x, mir);
+            else if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) block_iter(x, mir);
+            else cg_iter(x, mir);
             if (!poll_here) continue;
             WL_HIP(hipEventRecord(ring_ev[slot], ctx->stream));
             enq++;
@@ -377,6 +423,33 @@ class EoCore {
             run_blas(BL_XR_UPDATE, a, vec_bytes(P, 5) + vec_bytes(x.prec, 2));
             finalize(FIN_BICG_RHO, 3, nb, sin(), PH_RUN | PH_SCONV, mir);
         }
+    }
+
+    // One block BiCGStab iteration (block.hip has the recurrence); x in FP64.
+    void block_iter(Spinor x, RhsState *mir) {
+        Spinor none;
+        const double u = vec_bytes(P64, 1);  // one field of every right-hand side
+        apply_M(v.f, p.f, tmp.f, false, RED_NONE, none, sin(), PH_RUN);  // V = A P
+        BlockArgs a = block_args(sin());
+        a.a = rh.f; a.b = v.f; a.c = r.f;
+        run_block(BK_GRAM, 2, a, 3 * u);                                  // R~^H V, R~^H R
+        run_block(BK_SOLVE, BS_ALPHA, block_args(sin()), 0.0);
+        a = block_args(sin());
+        a.a = s.f; a.b = r.f; a.c = v.f;
+        run_block(BK_UPDATE, BU_S, a, 3 * u);                             // S = R - V alpha
+        const int hb = apply_M(t.f, s.f, tmp.f, false, RED_TS, none, sin(), PH_RUN);  // T = A S
+        finalize(FIN_BLOCK_TS, 3, hb, sin(), PH_RUN);
+        a = block_args(sin());
+        a.a = rh.f; a.b = t.f;
+        run_block(BK_GRAM, 1, a, 2 * u);                                  // R~^H T
+        run_block(BK_SOLVE, BS_BETA, block_args(sin()), 0.0);             // omega, beta
+        a = block_args(sin());
+        a.a = p.f; a.b = s.f; a.c = r.f; a.d = t.f; a.x = x;
+        run_block(BK_UPDATE, BU_XR, a, 6 * u);                            // X, R, |R_j|^2
+        run_block(BK_SOLVE, BS_CHECK, block_args(sin(), mir), 0.0);
+        a = block_args(sin());
+        a.a = p.f; a.b = r.f; a.c = v.f;
+        run_block(BK_UPDATE, BU_P, a, 4 * u);                             // P = R + (P - omega V) beta
     }
 
     void cg_iter(Spinor x, RhsState *mir) {
@@ -448,7 +521,12 @@ size_t solve_footprint(const Geom &g, int nrhs, const SolveParams &p) {
     auto fb = [&](int prec) { return (size_t)nrhs * spinor_field_bytes(prec, g); };
     size_t b = 5 * fb(P64) + 7 * fb(P);
     if (mixed) b += 2 * fb(P64) + fb(P) + fb(PX);
-    b += partials_doubles(g, nrhs) * sizeof(double) + 2 * sizeof(RhsState) * nrhs;
+    size_t npart = partials_doubles(g, nrhs);
+    if (p.method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
+        npart = std::max(npart, block_partials_doubles(g));
+        b += sizeof(BlockState);
+    }
+    b += npart * sizeof(double) + 2 * sizeof(RhsState) * nrhs;
     return b;
 }
 
@@ -500,7 +578,77 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
         for (int k = 0; k < nrhs; k++) res2[k] = h[k].aux;
     };
 
-    if (!C.mixed) {
+    if (prm.method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
+        // Blocks of up to kMaxBlock consecutive non-zero right-hand sides, one after the
+        // other; a zero right-hand side has the solution 0 and stays out of every block.
+        std::vector<int> fail(nrhs, FAIL_NONE);
+        for (int k = 0; k < nrhs; k++)
+            if (bn2[k] == 0.0) {
+                C.select(k, 1);
+                WL_HIP(launch_zero(C.V(C.x_e.f), g, 1, ctx->stream));
+            }
+        int k = 0;
+        while (k < nrhs) {
+            if (bn2[k] == 0.0) { k++; continue; }
+            const int c0 = k;
+            while (k < nrhs && bn2[k] > 0.0 && k - c0 < kMaxBlock) k++;
+            const int cn = k - c0;
+            C.select(c0, cn);
+            const std::vector<double> st2(stop2.begin() + c0, stop2.begin() + c0 + cn);
+            std::vector<char> act(cn, 1);
+            bool use_x0 = prm.use_x0, single = false;
+            int used_c = 0;
+            for (int attempt = 0;; attempt++) {
+                const int budget = prm.maxiter - used_c;
+                if (budget <= 0) break;
+                // after a breakdown of the block: one recurrence per right-hand side
+                C.method = single ? WILSON_SOLVER_BICGSTAB_EO : WILSON_SOLVER_BLOCK_BICGSTAB_EO;
+                std::vector<RhsState> fin;
+                try {
+                    fin = C.inner_solve(C.bp.f, C.x_e.f, use_x0, act, st2, budget, prm.poll_every);
+                } catch (...) {
+                    C.method = WILSON_SOLVER_BLOCK_BICGSTAB_EO;
+                    throw;
+                }
+                C.method = WILSON_SOLVER_BLOCK_BICGSTAB_EO;
+                int mx = 0;
+                for (int j = 0; j < cn; j++)
+                    if (act[j]) {
+                        iters[c0 + j] += fin[j].iter;
+                        mx = std::max(mx, fin[j].iter);
+                    }
+                used_c += std::max(mx, 1);
+                C.reconstruct();
+                C.true_residual2();
+                std::vector<RhsState> h = C.read_states(C.sout());
+                bool all_ok = true, broke = false, nonfinite = false;
+                for (int j = 0; j < cn; j++) {
+                    res2[c0 + j] = h[j].aux;
+                    if (act[j]) fail[c0 + j] = fin[j].phase == PH_FAIL ? fin[j].fail : FAIL_NONE;
+                    broke |= fail[c0 + j] == FAIL_BREAKDOWN;
+                    nonfinite |= fail[c0 + j] == FAIL_NONFINITE;
+                    all_ok &= res2[c0 + j] <= st2[j];
+                }
+                if (all_ok || nonfinite) break;
+                if (attempt >= prm.max_restarts || used_c >= prm.maxiter) break;
+                if (broke) single = true;
+                for (int j = 0; j < cn; j++) {
+                    if (single) act[j] = res2[c0 + j] > st2[j];
+                    if (act[j]) restarts[c0 + j]++;
+                }
+                use_x0 = true;
+            }
+        }
+        C.select_all();
+        true_check();
+        for (int j = 0; j < nrhs; j++) {
+            if (bn2[j] == 0.0) continue;
+            if (fail[j] == FAIL_NONFINITE) status[j] = WILSON_NONFINITE;
+            else if (res2[j] <= stop2[j]) status[j] = WILSON_OK;
+            else if (fail[j] == FAIL_BREAKDOWN) status[j] = WILSON_BREAKDOWN;
+            else status[j] = WILSON_NOT_CONVERGED;
+        }
+    } else if (!C.mixed) {
         bool use_x0 = prm.use_x0;
         for (int attempt = 0;; attempt++) {
             std::vector<char> active(nrhs);
