@@ -11,7 +11,8 @@ over the timed region) against the MI355X HBM peak, a Dslash-only figure (parity
 alone), and the CPU oracle timed on a bounded sample of the same workload.
 
 Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | mixed48_fp16h |
-batched24 | batched24_fp16 | clover32 | clover32_mixed | serve.
+mixed48_reliable | mixed48_fp16_reliable | batched24 | batched24_fp16 | block24 | block24_k135 |
+clover32 | clover32_mixed | serve | layouts.
 """
 import argparse
 import json
@@ -105,9 +106,16 @@ WORKLOADS = {
     "mixed48_fp16_reliable": ((48, 48, 48, 96), 0.125, 1e-10, 3, 1,
                               "mixed precision with reliable updates (FP16 spinors + per-site scale, FP32 links), "
                               "48^3x96, kappa=0.125, tol=1e-10"),
+    "block24": ((24, 24, 24, 48), 0.125, 1e-10, 0, 12,
+                "12 point sources solved together by block BiCGStab (one Krylov space, s = 12), FP64, 24^3x48, "
+                "kappa=0.125"),
+    "block24_k135": ((24, 24, 24, 48), 0.135, 1e-10, 0, 12,
+                     "12 point sources solved together by block BiCGStab (one Krylov space, s = 12), FP64, "
+                     "24^3x48, kappa=0.135 (closer to critical)"),
 }
 CLOVER = {"clover32", "clover32_mixed"}
 RELIABLE = {"mixed48_reliable", "mixed48_fp16_reliable"}
+BLOCK = {"block24", "block24_k135"}
 
 
 def run_serving(args):
@@ -391,7 +399,7 @@ def run_layouts(args):
     }
 
 
-def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check=None):
+def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check=None, block=False):
     """The FP64 oracle timed on the host: an even-odd BiCGStab solve (run for 1 and 1+k
     iterations, whose difference isolates the cost of an iteration, scaled to the number
     of iterations the GPU solve took), and the operator units (parity hop, full D) with
@@ -408,6 +416,8 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
     Fn = None if F is None else F.cpu().numpy()
 
     def solve(iters):
+        if block:  # the oracle's block BiCGStab on all the right-hand sides
+            return oracle.solve_block(b.cpu().numpy(), Un, kappa, dims, 0.0, iters, F=Fn)
         if Fn is None:
             return oracle.solve(bn, Un, kappa, dims, 0.0, iters, "bicgstab_eo")
         return oracle.solve_clov(bn, Un, Fn, kappa, dims, 0.0, iters, "bicgstab_eo")
@@ -459,14 +469,16 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
                         f" in the workload's precision ({['fp64', 'fp32', 'fp16', 'fp16 spinors + fp32 links'][precision]})",
         }
     what = ("the same right-hand side" if nrhs == 1 else
+            f"all {nrhs} right-hand sides in the oracle's block BiCGStab" if block else
             f"right-hand side 0 of the {nrhs}, the batch costed as {nrhs} sequential solves")
     inner = "" if precision == 0 else " (the GPU's inner iterations in reduced precision; the oracle is FP64)"
     return {
-        "value": 1.0 / (setup + per_iter * it_gpu),
+        "value": (nrhs if block else 1.0) / (setup + per_iter * it_gpu),
         "unit": "solves/s",
         "cores": nthr,
         "kind": "oracle",
-        "sample": f"FP64 oracle even-odd BiCGStab{' (clover matrix)' if Fn is not None else ''} on {list(dims)}, "
+        "sample": f"FP64 oracle even-odd {'block ' if block else ''}BiCGStab"
+                  f"{' (clover matrix)' if Fn is not None else ''} on {list(dims)}, "
                   f"{what}, run for 1 and {1 + k_it} "
                   f"iterations ({one + more:.1f} s of CPU work); solve time = setup + per-iteration cost x "
                   f"the {it_gpu:.0f} iterations the GPU solve needed{inner}",
@@ -526,6 +538,7 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     opts = {"precision": precision, "maxiter": 20000, "mixed_update": 1 if args.workload in RELIABLE else 0,
+            "solver": L.WILSON_SOLVER_BLOCK_BICGSTAB_EO if args.workload in BLOCK else L.WILSON_SOLVER_BICGSTAB_EO,
             "inner_tol": args.inner_tol}
 
     # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload);
@@ -694,7 +707,8 @@ def main():
             s0 = time.perf_counter()
             for k in range(nrhs):
                 xk = torch.zeros_like(srcs[0][k])
-                st, _ = L.wilson_solve_ex(ctx, g, xk, srcs[0][k].contiguous(), 1, kappa, tol, opts)
+                st, _ = L.wilson_solve_ex(ctx, g, xk, srcs[0][k].contiguous(), 1, kappa, tol,
+                                          dict(opts, solver=L.WILSON_SOLVER_BICGSTAB_EO))
                 L.check(st, "sequential solve")
             torch.cuda.synchronize()
             seq_t.append(time.perf_counter() - s0)
@@ -723,6 +737,28 @@ def main():
                      "solves": nref, "gain_solves_per_s": (solves / total) / f_val,
                      "gain_p99": percentile(f_lat, 99) / percentile(lat, 99)}
 
+    # ---- block workloads: the same batch with one BiCGStab recurrence per right-hand side
+    # (all of them in the same launches) ----
+    lockstep = None
+    if args.workload in BLOCK:
+        l_lat, l_it = [], []
+        lopts = dict(opts, solver=L.WILSON_SOLVER_BICGSTAB_EO)
+        x.zero_()
+        L.check(L.wilson_solve_ex(ctx, g, x, srcs[0], nrhs, kap, tl, lopts)[0], "lockstep warm-up solve")
+        torch.cuda.synchronize()
+        nref = min(args.steps, 5)
+        for i in range(nref):
+            s0 = time.perf_counter()
+            st, info = L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, lopts)
+            l_lat.append(time.perf_counter() - s0)
+            L.check(st, "lockstep solve")
+            l_it.append(max(d["iterations"] for d in info))
+        l_val = nref * nrhs / sum(l_lat)
+        lockstep = {"value": l_val, "unit": "solves/s", "ms_per_batch": 1e3 * float(np.median(l_lat)),
+                    "iterations_median": float(np.median(l_it)), "batches": nref,
+                    "gain_of_block": (solves / total) / l_val,
+                    "iteration_ratio": float(np.median(l_it)) / float(np.median(iters))}
+
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu:
@@ -731,12 +767,13 @@ def main():
         xr = x_last
         xbr = (srcs[j][0] if nrhs > 1 else srcs[j]).cpu().numpy()
         din = xbr
+        gpar = 2 if nrhs > 1 else dpar  # a point source has one parity: grade the full D on it
         dout_t = torch.zeros_like(srcs[j][0] if nrhs > 1 else srcs[j])
-        L.check(L.wilson_dslash_ex(ctx, g, dout_t, srcs[j][0].contiguous() if nrhs > 1 else srcs[j], kappa, dpar,
+        L.check(L.wilson_dslash_ex(ctx, g, dout_t, srcs[j][0].contiguous() if nrhs > 1 else srcs[j], kappa, gpar,
                                    dprec, 1), "graded dslash")
         dout = dout_t.cpu().numpy()
         cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)), F,
-                           check=(xr, xbr, dout, din, dpar))
+                           check=(xr, xbr, dout, din, gpar), block=args.workload in BLOCK)
 
     line = {
         "metric": METRIC,
@@ -764,6 +801,7 @@ def main():
         "cpu_baseline": cpu,
         "sequential_single_rhs": sequential,
         "fp64_same_problem": fp64_same,
+        "lockstep_same_batch": lockstep,
         "hbm_copy_gbs": copy_gbs,
         "hbm_read_gbs": read_gbs,
         "setup_s": setup_s,

@@ -47,65 +47,76 @@ __device__ __forceinline__ void stc(const dvec2 *p, int i, dcx v) {
 
 // ---------------------------------------------------------------------------------
 // Gram products G_p[i][j] = sum over sites and components of conj(A_i) B_p,j.
-// A wavefront holds 4 rows i (16 lanes each) over 16 consecutive sites of one component
-// plane; ceil(s/4) waves per block cover all rows, so the B loads of a tile are shared
-// by the rows of a wave (same addresses) and by the waves of the block (L1/L2).  Each
-// lane accumulates its row against all s columns; the 16 lanes of a row are then summed
-// with lane exchanges and each block writes one partial per value.
-constexpr int kGramSites = 16;
+// Register tiles of 4 rows x 4 columns: the wave (rg, cg) of a block owns rows
+// 4rg..4rg+3 and columns 4cg..4cg+3, its 64 lanes 64 consecutive sites of one component
+// plane, so every load of a wave is one contiguous 1 KB run.  A lane loads 4 elements of
+// A and 4 of B per tile and does 16 complex multiply-adds with them; the ceil(s/4)^2 waves
+// of a block share each A and B run through L1 (each is loaded by ceil(s/4) waves).  With
+// two operands B_0, B_1, blockIdx.y picks one (a block holding both would need more than
+// the registers of 9 waves).  At the end each wave sums its 64 lanes and writes one
+// partial per value.
+constexpr int kGramSites = 64;
 
-template <int NP>
-__global__ void __launch_bounds__(256) block_gram_kernel(const BlockArgs a) {
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) block_gram_kernel(const BlockArgs a) {
     if (!block_running(a)) return;
     const int s = a.s, Vh = a.g.Vh, stride = a.g.stride;
-    const int lane = threadIdx.x & 63;
-    const int row = (threadIdx.x >> 6) * 4 + (lane >> 4);
-    const int sub = lane & 15;
-    const bool rowok = row < s;
+    const int p = blockIdx.y;
+    const void *bdata = p == 0 ? a.b.data : a.c.data;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ng = (s + 3) >> 2;
+    const int rg = w / ng, cg = w - (w / ng) * ng;
     const int tps = (Vh + kGramSites - 1) / kGramSites;
     const int ntiles = 12 * tps;
-    dcx acc[NP][kMaxBlock];
+    dcx acc[4][4];
 #pragma unroll
-    for (int p = 0; p < NP; p++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < kMaxBlock; j++) acc[p][j] = {0.0, 0.0};
+        for (int j = 0; j < 4; j++) acc[i][j] = {0.0, 0.0};
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int c = tile / tps;
-        const int site = (tile - c * tps) * kGramSites + sub;
-        const int si = site < Vh ? site : Vh - 1;
-        dcx av = ldc(fplane_lane(a.a.data, (rowok ? row : 0) * 12 + c, stride), si);  // row differs per lane
-        if (!rowok || site >= Vh) av = {0.0, 0.0};
+        const int site = (tile - c * tps) * kGramSites + lane;
+        const bool ok = site < Vh;
+        const int si = ok ? site : Vh - 1;
+        dcx av[4], bv[4];
 #pragma unroll
-        for (int j = 0; j < kMaxBlock; j++) {
-            if (j < s) {
-                acc[0][j] = cfma_conj(acc[0][j], av, ldc(fplane(a.b.data, j * 12 + c, stride), si));
-                if constexpr (NP == 2)
-                    acc[1][j] = cfma_conj(acc[1][j], av, ldc(fplane(a.c.data, j * 12 + c, stride), si));
-            }
+        for (int i = 0; i < 4; i++) {
+            const int row = 4 * rg + i < s ? 4 * rg + i : s - 1;
+            av[i] = ldc(fplane(a.a.data, row * 12 + c, stride), si);
+            if (!ok) av[i] = {0.0, 0.0};
         }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int col = 4 * cg + j < s ? 4 * cg + j : s - 1;
+            bv[j] = ldc(fplane(bdata, col * 12 + c, stride), si);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = cfma_conj(acc[i][j], av[i], bv[j]);
     }
+    // sum the 64 lanes (fixed butterfly order) and write the wave's entries
 #pragma unroll
-    for (int p = 0; p < NP; p++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < kMaxBlock; j++) {
-            if (j < s) {
+        for (int j = 0; j < 4; j++) {
 #pragma unroll
-                for (int off = 8; off >= 1; off >>= 1) {
-                    acc[p][j].re += __shfl_xor(acc[p][j].re, off, 64);
-                    acc[p][j].im += __shfl_xor(acc[p][j].im, off, 64);
-                }
+            for (int off = 32; off >= 1; off >>= 1) {
+                acc[i][j].re += __shfl_xor(acc[i][j].re, off, 64);
+                acc[i][j].im += __shfl_xor(acc[i][j].im, off, 64);
             }
         }
-    if (sub == 0 && rowok) {
+    if (lane == 0) {
         const size_t nb = a.nblk;
 #pragma unroll
-        for (int p = 0; p < NP; p++)
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int j = 0; j < kMaxBlock; j++) {
-                if (j < s) {
-                    const size_t v = ((size_t)(p * s + row) * s + j) * 2;
-                    a.partials[v * nb + blockIdx.x] = acc[p][j].re;
-                    a.partials[(v + 1) * nb + blockIdx.x] = acc[p][j].im;
+            for (int j = 0; j < 4; j++) {
+                const int row = 4 * rg + i, col = 4 * cg + j;
+                if (row < s && col < s) {
+                    const size_t v = ((size_t)(p * s + row) * s + col) * 2;
+                    a.partials[v * nb + blockIdx.x] = acc[i][j].re;
+                    a.partials[(v + 1) * nb + blockIdx.x] = acc[i][j].im;
                 }
             }
     }
@@ -133,9 +144,14 @@ hipError_t launch_block_gram(BlockArgs a, int np, hipStream_t s) {
     if (a.s < 1 || a.s > kMaxBlock || (np != 1 && np != 2)) return hipErrorInvalidValue;
     const int ntiles = 12 * ((a.g.Vh + kGramSites - 1) / kGramSites);
     a.nblk = std::min(ntiles, kGramBlocks);
-    const dim3 block(64 * ((a.s + 3) / 4));
-    if (np == 1) hipLaunchKernelGGL(block_gram_kernel<1>, dim3(a.nblk), block, 0, s, a);
-    else hipLaunchKernelGGL(block_gram_kernel<2>, dim3(a.nblk), block, 0, s, a);
+    const int ng = (a.s + 3) / 4;
+    const dim3 grid(a.nblk, np), block(64 * ng * ng);
+    switch (ng) {
+        case 1: hipLaunchKernelGGL(block_gram_kernel<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(block_gram_kernel<4>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(block_gram_kernel<9>, grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL(block_gram_kernel<16>, grid, block, 0, s, a); break;
+    }
     hipLaunchKernelGGL(block_gram_reduce_kernel, dim3(np * a.s * a.s * 2), dim3(256), 0, s, a);
     return hipGetLastError();
 }
