@@ -8,7 +8,9 @@ BiCGStab and its FP64 operators:
     and split the blocks;
   * dependent right-hand sides break the block down; the library restarts with one
     recurrence per column and still converges;
-  * argument errors, bitwise reproducibility, restart from the returned solution."""
+  * argument errors, bitwise reproducibility, restart from the returned solution;
+  * iterations enqueued ahead of the host's poll are no-ops once the block is done;
+  * one column reproduces the BiCGStab solver's iterates."""
 import numpy as np
 import pytest
 import torch
@@ -163,5 +165,45 @@ def test_argument_errors(L, ctx):
             L.wilson_batch_create(ctx, g, 2, blk)
         st, _ = L.wilson_solve_ex(ctx, g, x, B, 2, [0.12, 0.12], [1e-8, 1e-8], blk)
         assert st == 0
+    finally:
+        L.wilson_gauge_free(ctx, g)
+
+
+def test_iterations_enqueued_ahead_change_nothing(L, ctx):
+    """With polls every 7 iterations the device runs past convergence in no-op launches
+    (every block kernel checks the block's phase): same iterations, bitwise same x."""
+    dims, k, tol = (8, 8, 8, 8), 0.125, 1e-10
+    U = inputs.gauge_field(dims, eps=0.3, seed=2260)
+    B = inputs.gaussian_source(dims, seed=2261, nrhs=6)
+    g = L.wilson_gauge_load(ctx, U.to(DEV), dims, 0)
+    try:
+        st1, info1, x1 = block_solve(L, ctx, g, B, k, tol, poll_every=1)
+        st7, info7, x7 = block_solve(L, ctx, g, B, k, tol, poll_every=7)
+        assert st1 == st7 == 0
+        assert [d["iterations"] for d in info1] == [d["iterations"] for d in info7]
+        assert np.array_equal(x1, x7)
+    finally:
+        L.wilson_gauge_free(ctx, g)
+
+
+def test_one_column_equals_bicgstab_solver(L, ctx):
+    """s = 1: the block kernels reproduce the BiCGStab solver's iterates (different kernels
+    and summation orders, the same recurrence)."""
+    dims, k = (8, 8, 8, 8), 0.125
+    U = inputs.gauge_field(dims, eps=0.3, seed=2270)
+    b = inputs.gaussian_source(dims, seed=2271, nrhs=1)
+    g = L.wilson_gauge_load(ctx, U.to(DEV), dims, 0)
+    try:
+        for it in (2, 7):
+            _, _, xb = block_solve(L, ctx, g, b, k, 1e-14, maxiter=it, max_restarts=0)
+            x = torch.zeros_like(b[0], device=DEV)
+            st, _ = L.wilson_solve_ex(ctx, g, x, b[0].to(DEV), 1, k, 1e-14,
+                                      {"maxiter": it, "max_restarts": 0})
+            assert st == L.WILSON_NOT_CONVERGED
+            assert rel(xb[0], x.cpu().numpy()) < 1e-12
+        st, info, xb = block_solve(L, ctx, g, b, k, 1e-10)
+        x = torch.zeros_like(b[0], device=DEV)
+        st2, info2 = L.wilson_solve_ex(ctx, g, x, b[0].to(DEV), 1, k, 1e-10, {})
+        assert st == st2 == 0 and abs(info[0]["iterations"] - info2[0]["iterations"]) <= 1
     finally:
         L.wilson_gauge_free(ctx, g)
