@@ -125,7 +125,15 @@ typedef struct {
     int32_t converged;     /* 1 if |b - D x| / |b| < tol in FP64 */
     double true_residual;  /* |b - D x| / |b| recomputed in FP64 after the solve */
     double ms;             /* wall time of the call on the host */
-    double hop_launches;   /* parity-hop launches issued */
+    double hop_launches;   /* parity-hop launches issued (this and the next two: for the
+                              whole call, the same in every record) */
+    double bytes;          /* algorithmic bytes of the call's parity hops and solver vector
+                              kernels: each operand field read or written once per launch,
+                              a link counted as 18 reals (conversions at the boundary and
+                              the scalar steps not included) */
+    double flops;          /* operator flops of those hops: 1320 per output site and
+                              right-hand side (Table 1's convention), 1896 with a clover
+                              site term; vector-kernel flops not included */
 } wilson_solve_info;
 
 /* ---------------------------------------------------------------------------------- */

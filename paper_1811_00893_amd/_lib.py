@@ -53,7 +53,7 @@ class wilson_solve_opts(ctypes.Structure):
 class wilson_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("outer_cycles", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("true_residual", ctypes.c_double), ("ms", ctypes.c_double),
-                ("hop_launches", ctypes.c_double)]
+                ("hop_launches", ctypes.c_double), ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -366,6 +366,8 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
     // its order and block, fit the RHS split
     cfg = fit_cfg(a, cfg);
     ctx->hop_launch_count++;
+    ctx->bytes_issued += algorithmic_bytes;
+    ctx->flops_issued += (a.clov_mode != CLV_NONE ? 1896.0 : 1320.0) * a.g.Vh * a.nrhs;
     if (ctx->timing) {
         hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
         WL_HIP(hipEventRecord(e0, ctx->stream));
@@ -379,6 +381,7 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
 }
 
 void blas(wilson_ctx *ctx, int op, BlasArgs &a, double algorithmic_bytes) {
+    ctx->bytes_issued += algorithmic_bytes;
     if (ctx->timing) {
         hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
         WL_HIP(hipEventRecord(e0, ctx->stream));

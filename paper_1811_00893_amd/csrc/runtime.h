@@ -150,6 +150,8 @@ struct wilson_ctx {
     int64_t launches[WILSON_KERNEL_COUNT] = {0, 0};
     double t_bytes[WILSON_KERNEL_COUNT] = {0, 0};
     int64_t hop_launch_count = 0;  // always counted
+    double bytes_issued = 0.0;     // algorithmic bytes of hop, vector and block kernels launched
+    double flops_issued = 0.0;     // operator flops of the hops launched
 
     hipEvent_t get_event();
     void drain_timing();  // resolves pending event pairs (waits for them)
@@ -177,6 +179,7 @@ void blas(wilson_ctx *ctx, int op, BlasArgs &a, double algorithmic_bytes);
 // Launch any kernel sequence through `launch` (returning hipError_t), timed as class cls.
 template <typename F>
 void timed_launch(wilson_ctx *ctx, int cls, double algorithmic_bytes, F &&launch) {
+    ctx->bytes_issued += algorithmic_bytes;
     if (ctx->timing) {
         hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
         WL_HIP(hipEventRecord(e0, ctx->stream));

@@ -534,6 +534,7 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
                  const double *kappa, const double *tol, const SolveParams &prm, wilson_solve_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t hop0 = ctx->hop_launch_count;
+    const double bytes0 = ctx->bytes_issued, flops0 = ctx->flops_issued;
     auto core = get_core(ctx, G, nrhs, prm);
     EoCore &C = *core;
     const Geom &g = C.g;
@@ -840,6 +841,8 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
             info[k].true_residual = bn2[k] > 0 ? std::sqrt(res2[k] / bn2[k]) : 0.0;
             info[k].ms = ms;
             info[k].hop_launches = (double)(ctx->hop_launch_count - hop0);
+            info[k].bytes = ctx->bytes_issued - bytes0;
+            info[k].flops = ctx->flops_issued - flops0;
         }
     }
     return worst;
@@ -1140,6 +1143,8 @@ class BatchEngine {
             info->true_residual = s.bn2 > 0 ? std::sqrt(s.res2 / s.bn2) : 0.0;
             info->ms = s.ms;
             info->hop_launches = 0;
+            info->bytes = 0;
+            info->flops = 0;
         }
         const int st = s.status;
         s.state = FREE;

@@ -395,3 +395,28 @@ def test_solve_bitwise_reproducible(L, ctx, prec):
         assert torch.equal(xs[1], xs[2]) and its[1] == its[2]
     finally:
         L.wilson_gauge_free(ctx, g)
+
+
+def test_solve_info_counts_bytes_and_flops(L, ctx):
+    """info.flops is 1320 operator flops per output site, right-hand side and hop launch;
+    info.bytes is at least the hops' own algorithmic bytes (per output site in FP64: the
+    8 links of 18 reals once for all right-hand sides, 24 reals in and 24 out per
+    right-hand side) plus the 14 fused vector-field streams per BiCGStab iteration."""
+    dims = (8, 8, 8, 8)
+    U, b = setup_case(dims, 61)
+    Vh = int(np.prod(dims)) // 2
+    g = L.wilson_gauge_load(ctx, U.to(DEV), dims, 0)
+    try:
+        nrhs = 3
+        bb = inputs.gaussian_source(dims, seed=2061, nrhs=nrhs).to(DEV)
+        x = torch.zeros_like(bb)
+        st, info = L.wilson_solve_ex(ctx, g, x, bb, nrhs, [0.12] * 3, [1e-10] * 3, {})
+        assert st == 0
+        d = info[0]
+        assert all(e["flops"] == d["flops"] and e["bytes"] == d["bytes"] for e in info)
+        assert d["flops"] == 1320.0 * Vh * nrhs * d["hop_launches"]
+        it = max(e["iterations"] for e in info)
+        low = d["hop_launches"] * Vh * (1152.0 + 384.0 * nrhs) + 14 * 192.0 * it * Vh * nrhs
+        assert low <= d["bytes"] < 2.0 * low
+    finally:
+        L.wilson_gauge_free(ctx, g)
