@@ -468,6 +468,17 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
             "operator": ("D_clov" if Fn is not None else ("parity hop" if dpar < 2 else "D")) +
                         f" in the workload's precision ({['fp64', 'fp32', 'fp16', 'fp16 spinors + fp32 links'][precision]})",
         }
+    host = {"cpu_model": None, "logical_cpus": os.cpu_count(), "cpus_in_affinity": len(os.sched_getaffinity(0)),
+            "omp_threads_used": nthr, "omp_proc_bind": os.environ.get("OMP_PROC_BIND"),
+            "omp_places": os.environ.get("OMP_PLACES")}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    host["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     what = ("the same right-hand side" if nrhs == 1 else
             f"all {nrhs} right-hand sides in the oracle's block BiCGStab" if block else
             f"right-hand side 0 of the {nrhs}, the batch costed as {nrhs} sequential solves")
@@ -493,6 +504,7 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
             "host_triad_gbs": triad,
         },
         "gpu_results_graded_by_oracle": graded,
+        "host": host,
     }
 
 
