@@ -44,3 +44,35 @@ def test_host_only_calls():
     # mixed FP32: 7 FP64 fields + 9 FP32 fields; plain FP64: 12 FP64 fields (plus small buffers)
     assert abs(fp32 / fp64 - 11.5 / 12) < 0.02
     assert _lib.wilson_footprint_bytes((8, 8, 8, 8), 12) > 11 * fp64
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of wilson_solve_opts and wilson_solve_info have the header's size
+    and field offsets (a C probe compiled against include/wilson.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_1811_00893_amd import _lib
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "wilson.h"', "int main(void) {"]
+    for st in (_lib.wilson_solve_opts, _lib.wilson_solve_info):
+        name = st.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in (_lib.wilson_solve_opts, _lib.wilson_solve_info):
+        name = st.__name__
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert got[(name, f)] == getattr(st, f).offset, (name, f)
