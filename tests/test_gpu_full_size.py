@@ -1,0 +1,110 @@
+"""Full-size checks in the benchmark's configurations: the solutions of the 32^3x64 FP64
+solve, the 48^3x96 mixed-precision solve and the 24^3x48 solves of 12 point sources (mixed
+batched and FP64 block), each graded by the oracle's FP64 operator on the whole lattice
+(|b - D x| / |b| < tol for every right-hand side), and the FP32 parity hop of the 48^3x96
+solve on sampled sites against the oracle evaluated site by site.  Inputs are the
+benchmark's seeds."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_00893_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1811_00893_amd import _lib
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.wilson_context_create()
+    yield c
+    L.wilson_context_destroy(c)
+
+
+def oracle_residual(x, b, U, k, dims):
+    return float(np.linalg.norm(b - oracle.apply_D(x, U, k, dims)) / np.linalg.norm(b))
+
+
+def run_solve(L, ctx, dims, k, tol, nrhs, opts, gauge_seed, point_sources, gbits):
+    print(f"full-size solve {dims} nrhs {nrhs} opts {opts}", flush=True)
+    U = inputs.gauge_field(dims, eps=0.3, seed=gauge_seed, device=DEV)
+    b = inputs.point_sources(dims, device=DEV) if point_sources else inputs.gaussian_source(dims, seed=2002,
+                                                                                         device=DEV)
+    g = L.wilson_gauge_load(ctx, U, dims, gbits)
+    try:
+        x = torch.zeros_like(b)
+        st, info = L.wilson_solve_ex(ctx, g, x, b, nrhs, [k] * nrhs, [tol] * nrhs, opts)
+        assert st == 0, (st, L.wilson_last_error())
+        torch.cuda.synchronize()
+        out = (U.cpu().numpy(), b.cpu().numpy(), x.cpu().numpy(), info)
+    finally:
+        L.wilson_gauge_free(ctx, g)
+        del U, b
+        torch.cuda.empty_cache()
+    return out
+
+
+def test_fp64_solve_32x32x32x64(L, ctx):
+    dims, k, tol = (32, 32, 32, 64), 0.125, 1e-10
+    Un, bn, xn, info = run_solve(L, ctx, dims, k, tol, 1, {"maxiter": 20000}, 1002, False, L.WILSON_GAUGE_FP32)
+    r = oracle_residual(xn, bn, Un, k, dims)
+    print(f"32^3x64 FP64: {info[0]['iterations']} iterations, oracle residual {r:.2e}")
+    assert r < tol and abs(r - info[0]["true_residual"]) < 0.01 * tol
+
+
+def test_mixed_solve_48x48x48x96(L, ctx):
+    dims, k, tol = (48, 48, 48, 96), 0.125, 1e-10
+    Un, bn, xn, info = run_solve(L, ctx, dims, k, tol, 1, {"precision": 1, "maxiter": 20000}, 1002, False,
+                                 L.WILSON_GAUGE_FP32)
+    r = oracle_residual(xn, bn, Un, k, dims)
+    print(f"48^3x96 mixed FP32: {info[0]['iterations']} inner iterations, oracle residual {r:.2e}")
+    assert r < tol
+
+
+@pytest.mark.parametrize("opts", [{"precision": 1}, {"solver": 2}], ids=["mixed_batched", "fp64_block"])
+def test_point_sources_24x24x24x48(L, ctx, opts):
+    dims, k, tol = (24, 24, 24, 48), 0.125, 1e-10
+    Un, bn, xn, info = run_solve(L, ctx, dims, k, tol, 12, dict(opts, maxiter=20000), 1002, True,
+                                 L.WILSON_GAUGE_FP32)
+    worst = max(oracle_residual(xn[j], bn[j], Un, k, dims) for j in range(12))
+    print(f"24^3x48 12 point sources {opts}: worst oracle residual {worst:.2e}")
+    assert worst < tol
+
+
+def test_fp32_hop_sampled_48x48x48x96(L, ctx):
+    """The FP32 parity hop of the mixed solve (inputs rounded to FP32), on 4096 sampled
+    output sites of each parity: relative error of the sampled vector below 5e-7 (FP32
+    rounding of inputs and arithmetic), exact zeros on the other parity."""
+    dims, k = (48, 48, 48, 96), 0.125
+    print("full-size FP32 hop 48^3x96", flush=True)
+    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=DEV)
+    psi = inputs.gaussian_source(dims, seed=2003, device=DEV)
+    g = L.wilson_gauge_load(ctx, U, dims, L.WILSON_GAUGE_FP32)
+    try:
+        Un, pn = U.cpu().numpy(), psi.cpu().numpy()
+        V = int(np.prod(dims))
+        par = oracle.parity_of_sites(dims)
+        rng = np.random.default_rng(6)
+        for p in (0, 1):
+            out = torch.zeros_like(psi)
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, k, p, 1), "dslash")
+            on = out.cpu().numpy()
+            sites = np.flatnonzero(par == p)
+            sites = np.concatenate([rng.choice(sites, 4096, replace=False), sites[:2], sites[-2:]])
+            ref = -k * oracle.hop_sites(pn, Un, dims, sites)
+            err = np.linalg.norm((on[sites] - ref).ravel()) / np.linalg.norm(ref.ravel())
+            print(f"parity {p}: sampled relative error {err:.2e}")
+            assert err < 5e-7
+            other = np.flatnonzero(par != p)[rng.choice(V // 2, 4096, replace=False)]
+            assert np.abs(on[other]).max() == 0.0
+    finally:
+        L.wilson_gauge_free(ctx, g)
+        del U, psi
+        torch.cuda.empty_cache()
