@@ -1,8 +1,9 @@
 """Full-size checks in the benchmark's configurations: the solutions of the 32^3x64 FP64
 solve, the 48^3x96 mixed-precision solve and the 24^3x48 solves of 12 point sources (mixed
 batched and FP64 block), each graded by the oracle's FP64 operator on the whole lattice
-(|b - D x| / |b| < tol for every right-hand side), and the FP32 parity hop of the 48^3x96
-solve on sampled sites against the oracle evaluated site by site.  Inputs are the
+(|b - D x| / |b| < tol for every right-hand side), the 32^3x64 clover solve graded by the
+oracle's D_clov, and the reduced-precision parity hops of the 48^3x96 solves on sampled
+sites against the oracle evaluated site by site.  Inputs are the
 benchmark's seeds."""
 import numpy as np
 import pytest
@@ -78,15 +79,17 @@ def test_point_sources_24x24x24x48(L, ctx, opts):
     assert worst < tol
 
 
-def test_fp32_hop_sampled_48x48x48x96(L, ctx):
-    """The FP32 parity hop of the mixed solve (inputs rounded to FP32), on 4096 sampled
-    output sites of each parity: relative error of the sampled vector below 5e-7 (FP32
-    rounding of inputs and arithmetic), exact zeros on the other parity."""
+@pytest.mark.parametrize("prec,limit", [(1, 5e-7), (3, 2e-3), (2, 2e-3)], ids=["fp32", "fp16_l32", "fp16"])
+def test_reduced_precision_hop_sampled_48x48x48x96(L, ctx, prec, limit):
+    """The parity hops of the mixed solves (inputs rounded to FP32, or to FP16 with a
+    per-site scale and FP32 or FP16 links), on 4096 sampled output sites of each parity:
+    relative error of the sampled vector below the precision's bound (as on small
+    lattices), exact zeros on the other parity."""
     dims, k = (48, 48, 48, 96), 0.125
-    print("full-size FP32 hop 48^3x96", flush=True)
+    print(f"full-size hop 48^3x96 precision {prec}", flush=True)
     U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=DEV)
     psi = inputs.gaussian_source(dims, seed=2003, device=DEV)
-    g = L.wilson_gauge_load(ctx, U, dims, L.WILSON_GAUGE_FP32)
+    g = L.wilson_gauge_load(ctx, U, dims, L.WILSON_GAUGE_FP32 | (L.WILSON_GAUGE_FP16 if prec == 2 else 0))
     try:
         Un, pn = U.cpu().numpy(), psi.cpu().numpy()
         V = int(np.prod(dims))
@@ -94,17 +97,41 @@ def test_fp32_hop_sampled_48x48x48x96(L, ctx):
         rng = np.random.default_rng(6)
         for p in (0, 1):
             out = torch.zeros_like(psi)
-            L.check(L.wilson_dslash_ex(ctx, g, out, psi, k, p, 1), "dslash")
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, k, p, prec), "dslash")
             on = out.cpu().numpy()
             sites = np.flatnonzero(par == p)
             sites = np.concatenate([rng.choice(sites, 4096, replace=False), sites[:2], sites[-2:]])
             ref = -k * oracle.hop_sites(pn, Un, dims, sites)
             err = np.linalg.norm((on[sites] - ref).ravel()) / np.linalg.norm(ref.ravel())
             print(f"parity {p}: sampled relative error {err:.2e}")
-            assert err < 5e-7
+            assert err < limit
             other = np.flatnonzero(par != p)[rng.choice(V // 2, 4096, replace=False)]
             assert np.abs(on[other]).max() == 0.0
     finally:
         L.wilson_gauge_free(ctx, g)
         del U, psi
         torch.cuda.empty_cache()
+
+
+def test_clover_solve_32x32x32x64(L, ctx):
+    """The clover workload (synthetic F, c = 0.05, the benchmark's seed) solved in FP64 and
+    graded by the oracle's D_clov = (1 + F) - kappa H on the whole lattice."""
+    dims, k, tol = (32, 32, 32, 64), 0.125, 1e-10
+    print("full-size clover solve 32^3x64", flush=True)
+    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=DEV)
+    F = inputs.clover_field(dims, c=0.05, seed=1005, device=DEV)
+    b = inputs.gaussian_source(dims, seed=2002, device=DEV)
+    g = L.wilson_gauge_load(ctx, U, dims, 0)
+    try:
+        L.check(L.wilson_gauge_attach_clover(ctx, g, F, dims), "attach clover")
+        x = torch.zeros_like(b)
+        st, info = L.wilson_solve_ex(ctx, g, x, b, 1, k, tol, {"maxiter": 20000})
+        assert st == 0, (st, L.wilson_last_error())
+        Un, Fn, bn, xn = U.cpu().numpy(), F.cpu().numpy(), b.cpu().numpy(), x.cpu().numpy()
+    finally:
+        L.wilson_gauge_free(ctx, g)
+        del U, F, b
+        torch.cuda.empty_cache()
+    r = float(np.linalg.norm(bn - oracle.apply_Dclov(xn, Un, Fn, k, dims)) / np.linalg.norm(bn))
+    print(f"32^3x64 clover FP64: {info[0]['iterations']} iterations, oracle residual {r:.2e}")
+    assert r < tol and abs(r - info[0]["true_residual"]) < 0.01 * tol
