@@ -2,8 +2,8 @@
 solve, the 48^3x96 mixed-precision solve and the 24^3x48 solves of 12 point sources (mixed
 batched and FP64 block), each graded by the oracle's FP64 operator on the whole lattice
 (|b - D x| / |b| < tol for every right-hand side), the 32^3x64 clover solve graded by the
-oracle's D_clov, and the reduced-precision parity hops of the 48^3x96 solves on sampled
-sites against the oracle evaluated site by site.  Inputs are the
+oracle's D_clov, the reduced-precision parity hops of the 48^3x96 solves and the 12-RHS
+hop of the 24^3x48 batches on sampled sites against the oracle evaluated site by site.  Inputs are the
 benchmark's seeds."""
 import numpy as np
 import pytest
@@ -135,3 +135,34 @@ def test_clover_solve_32x32x32x64(L, ctx):
     r = float(np.linalg.norm(bn - oracle.apply_Dclov(xn, Un, Fn, k, dims)) / np.linalg.norm(bn))
     print(f"32^3x64 clover FP64: {info[0]['iterations']} iterations, oracle residual {r:.2e}")
     assert r < tol and abs(r - info[0]["true_residual"]) < 0.01 * tol
+
+
+@pytest.mark.parametrize("prec,limit", [(0, 1e-12), (1, 5e-7), (3, 2e-3)], ids=["fp64", "fp32", "fp16_l32"])
+def test_multi_rhs_hop_sampled_24x24x24x48(L, ctx, prec, limit):
+    """The 12-RHS parity hop in the launch configuration the batched solves use (tuned on
+    these arguments), 12 Gaussian fields at once: for every right-hand side, 512 sampled
+    output sites against the oracle evaluated site by site."""
+    dims, k, nrhs = (24, 24, 24, 48), 0.125, 12
+    print(f"full-size 12-RHS hop 24^3x48 precision {prec}", flush=True)
+    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=DEV)
+    psi = inputs.gaussian_source(dims, seed=2004, nrhs=nrhs, device=DEV)
+    g = L.wilson_gauge_load(ctx, U, dims, L.WILSON_GAUGE_FP32)
+    try:
+        out = torch.zeros_like(psi)
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, k, 0, prec, nrhs), "dslash")
+        Un, pn, on = U.cpu().numpy(), psi.cpu().numpy(), out.cpu().numpy()
+        par = oracle.parity_of_sites(dims)
+        rng = np.random.default_rng(7)
+        even = np.flatnonzero(par == 0)
+        worst = 0.0
+        for j in range(nrhs):
+            sites = np.concatenate([rng.choice(even, 512, replace=False), even[:1], even[-1:]])
+            ref = -k * oracle.hop_sites(pn[j], Un, dims, sites)
+            err = np.linalg.norm((on[j][sites] - ref).ravel()) / np.linalg.norm(ref.ravel())
+            worst = max(worst, err)
+        print(f"worst sampled relative error over {nrhs} RHS: {worst:.2e}")
+        assert worst < limit
+    finally:
+        L.wilson_gauge_free(ctx, g)
+        del U, psi
+        torch.cuda.empty_cache()
