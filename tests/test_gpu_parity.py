@@ -420,3 +420,32 @@ def test_solve_info_counts_bytes_and_flops(L, ctx):
         assert low <= d["bytes"] < 2.0 * low
     finally:
         L.wilson_gauge_free(ctx, g)
+
+
+def test_maximum_rhs_count(L, ctx):
+    """64 right-hand sides (the largest batch one call takes): the parity hop in FP64, FP32
+    and FP16 against the oracle column by column, 65 rejected; the lockstep and the block
+    solver (four blocks of 16) solve all 64 to tolerance by the oracle's D."""
+    dims, k, n = (4, 4, 4, 8), 0.125, 64
+    U = inputs.gauge_field(dims, eps=0.3, seed=2300)
+    B = inputs.gaussian_source(dims, seed=2301, nrhs=n)
+    g = L.wilson_gauge_load(ctx, U.to(DEV), dims, L.WILSON_GAUGE_FP32 | L.WILSON_GAUGE_FP16)
+    try:
+        Bd = B.to(DEV)
+        for prec, limit in ((0, 1e-13), (1, 5e-7), (2, 2e-3)):
+            out = torch.zeros_like(Bd)
+            L.check(L.wilson_dslash_ex(ctx, g, out, Bd, k, 1, prec, n), "dslash")
+            o = out.cpu().numpy()
+            worst = max(rel(o[j], oracle.dslash(B[j].numpy(), U.numpy(), k, dims, 1)) for j in range(n))
+            assert worst < limit, (prec, worst)
+        big = inputs.gaussian_source(dims, seed=2302, nrhs=n + 1).to(DEV)
+        assert L.wilson_dslash_ex(ctx, g, torch.zeros_like(big), big, k, 1, 0, n + 1) == L.WILSON_INVALID_ARG
+        for solver in (L.WILSON_SOLVER_BICGSTAB_EO, L.WILSON_SOLVER_BLOCK_BICGSTAB_EO):
+            x = torch.zeros_like(Bd)
+            st, info = L.wilson_solve_ex(ctx, g, x, Bd, n, [k] * n, [1e-10] * n, {"solver": solver})
+            assert st == 0, (solver, st, L.wilson_last_error())
+            xn = x.cpu().numpy()
+            worst = max(oracle_residual(xn[j], B[j].numpy(), U.numpy(), k, dims) for j in range(n))
+            assert worst < 1e-10, (solver, worst)
+    finally:
+        L.wilson_gauge_free(ctx, g)
