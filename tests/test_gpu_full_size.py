@@ -3,8 +3,8 @@ solve, the 48^3x96 mixed-precision solve and the 24^3x48 solves of 12 point sour
 batched and FP64 block), each graded by the oracle's FP64 operator on the whole lattice
 (|b - D x| / |b| < tol for every right-hand side), the 32^3x64 clover solve graded by the
 oracle's D_clov, the reduced-precision parity hops of the 48^3x96 solves and the 12-RHS
-hop of the 24^3x48 batches on sampled sites against the oracle evaluated site by site.  Inputs are the
-benchmark's seeds."""
+hop of the 24^3x48 batches on sampled sites against the oracle evaluated site by site.
+Inputs are the benchmark's seeds."""
 import numpy as np
 import pytest
 import torch
