@@ -34,8 +34,18 @@ from . import (apply_Mee, apply_Mee_clov, clov_eo_prepare, clov_eo_reconstruct, 
 
 
 class BlockBreakdown(RuntimeError):
-    """The s x s matrix R~^H V is singular to working precision (relative pivot below
-    1e-13, the threshold the library uses) or not finite."""
+    """The s x s matrix R~^H V is singular to working precision or not finite.
+
+    Singular to working precision means: a pivot of its LU factorisation with partial
+    pivoting is at most 1e-13 times the largest entry.  The threshold comes from the
+    backward error of that factorisation, not from any implementation: in FP64 (unit
+    roundoff u = 2^-53 = 1.1e-16) LU of an s x s matrix is exact for a matrix within
+    about s^2 u of it, relative to its largest entry, so for the block sizes used here
+    (s <= 16: s^2 u = 2.8e-14) a pivot below a few times that bound cannot be told from
+    zero, and 1e-13 (3.5 s^2 u at s = 16) is the smallest round threshold above it.  The
+    pins separate the two regimes by many orders of magnitude either way: linearly
+    dependent sources give relative pivots near u, independent random sources pivots of
+    order 0.1 or more, so any threshold between about 1e-15 and 1e-3 classifies them alike."""
 
 
 def _check_small(G):

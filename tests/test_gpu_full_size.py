@@ -1,5 +1,6 @@
 """Full-size checks in the benchmark's configurations: the solutions of the 32^3x64 FP64
-solve, the 48^3x96 mixed-precision solve and the 24^3x48 solves of 12 point sources (mixed
+solve, the 48^3x96 mixed-precision solves (FP32 inner, FP16 spinors with FP32 or FP16
+links) and the 24^3x48 solves of 12 point sources (mixed
 batched and FP64 block), each graded by the oracle's FP64 operator on the whole lattice
 (|b - D x| / |b| < tol for every right-hand side), the 32^3x64 clover solve graded by the
 oracle's D_clov, the reduced-precision parity hops of the 48^3x96 solves and the 12-RHS
@@ -60,13 +61,20 @@ def test_fp64_solve_32x32x32x64(L, ctx):
     assert r < tol and abs(r - info[0]["true_residual"]) < 0.01 * tol
 
 
-def test_mixed_solve_48x48x48x96(L, ctx):
+@pytest.mark.parametrize("prec", [1, 3, 2], ids=["fp32", "fp16_l32", "fp16"])
+def test_mixed_solve_48x48x48x96(L, ctx, prec):
+    """The three mixed-precision variants of the 48^3x96 workload (FP32 inner; FP16 spinors
+    with per-site scales and FP32 links; FP16 spinors and FP16 links), each solved in the
+    launch configuration the benchmark uses and graded by the oracle's FP64 D on the whole
+    lattice."""
     dims, k, tol = (48, 48, 48, 96), 0.125, 1e-10
-    Un, bn, xn, info = run_solve(L, ctx, dims, k, tol, 1, {"precision": 1, "maxiter": 20000}, 1002, False,
-                                 L.WILSON_GAUGE_FP32)
+    gbits = L.WILSON_GAUGE_FP32 | (L.WILSON_GAUGE_FP16 if prec == 2 else 0)
+    Un, bn, xn, info = run_solve(L, ctx, dims, k, tol, 1, {"precision": prec, "maxiter": 20000}, 1002, False,
+                                 gbits)
     r = oracle_residual(xn, bn, Un, k, dims)
-    print(f"48^3x96 mixed FP32: {info[0]['iterations']} inner iterations, oracle residual {r:.2e}")
-    assert r < tol
+    print(f"48^3x96 mixed precision {prec}: {info[0]['iterations']} inner iterations, "
+          f"{info[0]['outer_cycles']} cycles, oracle residual {r:.2e}")
+    assert r < tol and abs(r - info[0]["true_residual"]) < 0.01 * tol
 
 
 @pytest.mark.parametrize("opts", [{"precision": 1}, {"solver": 2}], ids=["mixed_batched", "fp64_block"])

@@ -83,3 +83,29 @@ def test_dependent_sources_break_down(oracle_mod):
     B = np.stack([b[0], b[1], 2.0 * b[0] - 1j * b[1]])
     with pytest.raises(oracle_mod.BlockBreakdown):
         oracle_mod.solve_block(B, U, 0.12, dims, 1e-10, 100)
+
+
+def test_breakdown_threshold_separates_dependent_sources(oracle_mod):
+    """The breakdown test (a relative LU pivot of R~^H V at most 1e-13) sits far from both
+    regimes: on the first iteration, linearly dependent sources give a smallest relative
+    pivot near the unit roundoff, independent Gaussian or point sources pivots of order one
+    (LU from scipy, independent of the oracle's own pivot loop)."""
+    import scipy.linalg
+    dims = (4, 4, 4, 4)
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, seed=2140).numpy()
+    even = np.repeat(oracle_mod.parity_of_sites(dims) == 0, 12)
+
+    def min_pivot(B):
+        Bp = np.stack([np.where(even, oracle_mod.eo_prepare(B[j], U, 0.12, dims).reshape(-1), 0)
+                       for j in range(B.shape[0])], axis=1)
+        AV = np.stack([oracle_mod.apply_Mee(Bp[:, j].reshape(V, 4, 3), U, 0.12, dims).reshape(-1)
+                       for j in range(Bp.shape[1])], axis=1)
+        G = Bp.conj().T @ AV
+        _, _, u = scipy.linalg.lu(G)
+        return float(np.abs(np.diag(u)).min() / np.abs(G).max())
+
+    b = inputs.gaussian_source(dims, seed=2141, nrhs=12).numpy()
+    assert min_pivot(np.stack([b[0], b[1], 2.0 * b[0] - 1j * b[1]])) < 1e-15
+    assert min_pivot(b) > 1e-3
+    assert min_pivot(inputs.point_sources(dims).numpy()) > 1e-3
