@@ -116,6 +116,14 @@ typedef struct {
                               recurrence through all cycles; at each cycle the FP64 residual
                               replaces the iterated one; inner_tol is the drop per cycle
                               with the same defaults).  Batches take 0. */
+    void *workspace;       /* optional caller-owned device memory (e.g. a torch tensor's
+                              storage), 256-byte aligned, for every device buffer of the call:
+                              wilson_solve_ex uses it for that call only (nothing is kept in it
+                              afterwards), wilson_batch_create for the batch's lifetime (the
+                              caller keeps it alive until wilson_batch_destroy).  NULL: the
+                              library allocates and caches its own (the default). */
+    size_t workspace_bytes;/* size of workspace; at least wilson_footprint_bytes(dims, nrhs or
+                              nslots, opts), else the call fails with WILSON_INVALID_ARG */
 } wilson_solve_opts;
 
 typedef struct {
@@ -229,7 +237,8 @@ int wilson_solve_ex(wilson_ctx *ctx, const wilson_gauge *g, double *x, const dou
                     wilson_solve_info *info);
 
 /* Device bytes wilson_solve_ex would allocate for this lattice, nrhs and options
- * (workspace only; the resident gauge field is wilson_gauge_bytes). */
+ * (workspace only; the resident gauge field is wilson_gauge_bytes); also the smallest
+ * opts->workspace_bytes a caller-owned workspace may have. */
 size_t wilson_footprint_bytes(const int32_t dims[4], int32_t nrhs, const wilson_solve_opts *opts);
 
 /* ---------------------------------------------------------------------------------- */
@@ -238,7 +247,8 @@ size_t wilson_footprint_bytes(const int32_t dims[4], int32_t nrhs, const wilson_
 /* ---------------------------------------------------------------------------------- */
 
 /* A batch of `nslots` independent solves on one resident gauge field; all slots use
- * opts (solver, precision, inner_tol); kappa and tol are per slot. */
+ * opts (solver, precision, inner_tol; workspace, if given, holds the batch's device
+ * buffers until wilson_batch_destroy); kappa and tol are per slot. */
 int wilson_batch_create(wilson_ctx *ctx, const wilson_gauge *g, int32_t nslots, const wilson_solve_opts *opts,
                         wilson_batch **batch);
 int wilson_batch_destroy(wilson_batch *batch);

@@ -47,7 +47,8 @@ EXPORTS = [
 class wilson_solve_opts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32), ("maxiter", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int32),
-                ("poll_every", ctypes.c_int32), ("mixed_update", ctypes.c_int32)]
+                ("poll_every", ctypes.c_int32), ("mixed_update", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class wilson_solve_info(ctypes.Structure):
@@ -176,6 +177,10 @@ def _opts(opts):
     o.use_x0 = int(bool(opts.get("use_x0", False)))
     o.poll_every = int(opts.get("poll_every", 0))
     o.mixed_update = int(opts.get("mixed_update", 0))
+    ws = opts.get("workspace")
+    if ws is not None:  # a device tensor (its storage) or a raw address
+        o.workspace = ws.data_ptr() if isinstance(ws, torch.Tensor) else int(ws)
+        o.workspace_bytes = int(opts.get("workspace_bytes", _nbytes(ws) if isinstance(ws, torch.Tensor) else 0))
     return ctypes.byref(o)
 
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 
@@ -54,10 +55,11 @@ struct Staged {
 };
 
 wilson_ctx *make_ctx(void *stream) {
-    auto *c = new wilson_ctx();
+    std::unique_ptr<wilson_ctx> c(new wilson_ctx());
     WL_HIP(hipGetDevice(&c->device));
     c->stream = static_cast<hipStream_t>(stream);
-    return c;
+    c->lend.create(kMaxRhs);
+    return c.release();
 }
 
 wilson_ctx *default_ctx() {
@@ -152,6 +154,10 @@ static void check_solve_args(const double *kappa, const double *tol, int nrhs, c
         WL_CHECK_ARG(o->mixed_update == 0 || o->mixed_update == 1, "mixed_update must be 0 or 1");
         WL_CHECK_ARG(o->mixed_update == 0 || (o->precision != WILSON_FP64 && o->solver == WILSON_SOLVER_BICGSTAB_EO),
                      "reliable updates need a mixed precision and BiCGStab");
+        if (o->workspace) {
+            WL_CHECK_ARG(reinterpret_cast<uintptr_t>(o->workspace) % 256 == 0, "workspace must be 256-byte aligned");
+            WL_CHECK_ARG(is_device_ptr(o->workspace), "workspace must be device memory");
+        }
     }
 }
 
@@ -167,6 +173,8 @@ static SolveParams params_from(const wilson_solve_opts *o, int maxiter_default) 
         p.use_x0 = o->use_x0 != 0;
         p.poll_every = o->poll_every > 0 ? o->poll_every : 1;
         p.reliable = o->mixed_update == 1;
+        p.workspace = o->workspace;
+        p.workspace_bytes = o->workspace_bytes;
     }
     return p;
 }

@@ -81,6 +81,8 @@ inline size_t spinor_field_bytes(int prec, const Geom &g) {
 enum Phase : int { PH_IDLE = 1, PH_RUN = 2, PH_SCONV = 4, PH_DONE = 8, PH_FAIL = 16 };
 enum FailCode : int { FAIL_NONE = 0, FAIL_BREAKDOWN = 1, FAIL_NONFINITE = 2 };
 
+constexpr int kStateRing = 4;  // host-mapped state mirrors of a solve in flight
+
 struct alignas(16) RhsState {
     double rho_re, rho_im;      // <rhat, r>
     double alpha_re, alpha_im;

@@ -76,6 +76,19 @@ PinnedBuf::~PinnedBuf() {
     if (h_) (void)hipHostFree(h_);
 }
 
+void SolveHostRes::create(int nrhs) {
+    mirror.alloc(sizeof(RhsState) * nrhs * kStateRing);
+    hinit.alloc(sizeof(RhsState) * nrhs);
+    hread.alloc(sizeof(RhsState) * nrhs);
+    for (auto &e : ring) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    cap = nrhs;
+}
+
+SolveHostRes::~SolveHostRes() {
+    for (auto &e : ring)
+        if (e) (void)hipEventDestroy(e);
+}
+
 bool is_device_ptr(const void *p) {
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, p);

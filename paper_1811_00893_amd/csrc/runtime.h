@@ -79,6 +79,17 @@ class PinnedBuf {
 
 bool is_device_ptr(const void *p);
 
+// Host-side resources of one solve besides device memory: pinned, device-mapped per-RHS
+// state records (a ring of mirrors the host polls, one upload and one read buffer) and the
+// ring's events, for up to nrhs right-hand sides.
+struct SolveHostRes {
+    PinnedBuf mirror, hinit, hread;
+    hipEvent_t ring[kStateRing] = {};
+    int cap = 0;  // right-hand sides the buffers hold
+    void create(int nrhs);
+    ~SolveHostRes();
+};
+
 }  // namespace wl
 
 struct wilson_gauge {
@@ -158,6 +169,9 @@ struct wilson_ctx {
 
 
     // ---- scratch ----
+    // host resources lent to solves whose device memory the caller provides (created with
+    // the context, so those solves allocate nothing themselves)
+    wl::SolveHostRes lend;
     wl::DevBuf stage_in, stage_out;  // canonical staging for host pointers
     wl::DevBuf flag;                 // device int for finiteness checks
     wl::PinnedBuf pinned;            // small host mirror

@@ -19,6 +19,15 @@ void FieldBuf::make(int prec, const Geom &g, int nrhs) {
     f.prec = prec;
 }
 
+void FieldBuf::place(int prec, const Geom &g, int nrhs, Arena &A) {
+    const size_t data = (size_t)nrhs * 12 * spinor_plane_bytes(prec, g);
+    const size_t scl = prec == P16 ? (size_t)nrhs * g.stride * sizeof(float) : 0;
+    char *p = static_cast<char *>(A.take(data + scl));
+    f.data = p;
+    f.scale = prec == P16 && p ? reinterpret_cast<float *>(p + data) : nullptr;
+    f.prec = prec;
+}
+
 static inline int inner_prec(int precision) {
     switch (precision) {
         case WILSON_FP64: return P64;
@@ -35,11 +44,39 @@ static inline int inner_gauge_prec(int precision) {
     }
 }
 
-constexpr int kRing = 4;     // host-mapped state mirrors in flight
+constexpr int kRing = kStateRing;  // host-mapped state mirrors in flight
 constexpr int kAllPhases = PH_IDLE | PH_RUN | PH_SCONV | PH_DONE | PH_FAIL;
 
+size_t EoMem::carve(char *base, const Geom &g, int n, int precision, int method) {
+    const int P = inner_prec(precision), PX = P == P16 ? P32 : P;
+    const bool mixed = precision != WILSON_FP64;
+    Arena A;
+    A.base = base;
+    for (FieldBuf *f : {&b_e, &b_o, &x_e, &x_o, &bp}) f->place(P64, g, n, A);
+    if (mixed) {
+        r64.place(P64, g, n, A);
+        tmp64.place(P64, g, n, A);
+        rf.place(P, g, n, A);
+        xin.place(PX, g, n, A);
+    }
+    for (FieldBuf *f : {&r, &rh, &p, &v, &s, &t, &tmp}) f->place(P, g, n, A);
+    size_t npart = partials_doubles(g, n);
+    if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
+        npart = std::max(npart, block_partials_doubles(g));
+        bstate = static_cast<BlockState *>(A.take(sizeof(BlockState)));
+    }
+    partials = static_cast<double *>(A.take(npart * sizeof(double)));
+    st_in = static_cast<RhsState *>(A.take(sizeof(RhsState) * n));
+    st_out = static_cast<RhsState *>(A.take(sizeof(RhsState) * n));
+    bytes = (A.used + 255) & ~size_t(255);
+    return bytes;
+}
+
 // Fields, states and primitive operations of one even-odd problem with nrhs RHS.
-class EoCore {
+// Device memory: one region holding every buffer (EoMem), either allocated here or the
+// caller's workspace.  Host resources (pinned state mirrors, ring events): owned, or lent
+// by the context.
+class EoCore : public EoMem {
    public:
     wilson_ctx *ctx;
     const wilson_gauge *G;
@@ -53,46 +90,46 @@ class EoCore {
     // to one slot for per-slot bookkeeping; solves use the full range).
     int k0 = 0, nk = 0;
 
-    FieldBuf b_e, b_o, x_e, x_o, bp;         // FP64 problem
-    FieldBuf r64, tmp64;                     // FP64 outer residual (mixed only)
-    FieldBuf r, rh, p, v, s, t, tmp, rf, xin; // inner Krylov fields
-    DevBuf partials, st_in, st_out;
-    DevBuf bstate;  // block BiCGStab: the s x s matrices of the iteration
-    PinnedBuf mirror, hinit, hread;
-    hipEvent_t ring_ev[kRing] = {};
+    DevBuf own;                             // the region, when the library allocates it
+    std::unique_ptr<SolveHostRes> own_host; // host resources, when not lent
+    SolveHostRes *host = nullptr;
+    const hipEvent_t *ring_ev = nullptr;
 
-    EoCore(wilson_ctx *c, const wilson_gauge *gauge, int n, int precision, int meth)
+    // ws / ws_bytes: the caller's device region (null: allocate one); lent: host resources
+    // to use instead of allocating (at least n right-hand sides)
+    EoCore(wilson_ctx *c, const wilson_gauge *gauge, int n, int precision, int meth, void *ws = nullptr,
+           size_t ws_bytes = 0, SolveHostRes *lent = nullptr)
         : ctx(c), G(gauge), g(gauge->g), nrhs(n), method(meth), nk(n) {
         P = inner_prec(precision);
         GP = inner_gauge_prec(precision);
         PX = P == P16 ? P32 : P;
         mixed = precision != WILSON_FP64;
         if (!G->links(GP)) throw Error(WILSON_INVALID_ARG, "gauge field lacks the link precision requested");
-        b_e.make(P64, g, n); b_o.make(P64, g, n); x_e.make(P64, g, n); x_o.make(P64, g, n); bp.make(P64, g, n);
-        if (mixed) {
-            r64.make(P64, g, n); tmp64.make(P64, g, n);
-            rf.make(P, g, n); xin.make(PX, g, n);
+        const size_t need = carve(nullptr, g, n, precision, method);
+        char *base;
+        if (ws) {
+            if (ws_bytes < need)
+                throw Error(WILSON_INVALID_ARG, "workspace of " + std::to_string(ws_bytes) + " bytes is smaller than the " +
+                                                    std::to_string(need) + " bytes this solve needs");
+            if (reinterpret_cast<uintptr_t>(ws) % 256) throw Error(WILSON_INVALID_ARG, "workspace must be 256-byte aligned");
+            base = static_cast<char *>(ws);
+        } else {
+            own.alloc(need);
+            base = own.as<char>();
         }
-        r.make(P, g, n); rh.make(P, g, n); p.make(P, g, n); v.make(P, g, n); s.make(P, g, n); t.make(P, g, n);
-        tmp.make(P, g, n);
-        size_t npart = partials_doubles(g, n);
-        if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
-            npart = std::max(npart, block_partials_doubles(g));
-            bstate.alloc(sizeof(BlockState));
+        carve(base, g, n, precision, method);
+        if (lent) {
+            if (lent->cap < n) throw Error(WILSON_INVALID_ARG, "lent host resources too small");
+            host = lent;
+        } else {
+            own_host = std::make_unique<SolveHostRes>();
+            own_host->create(n);
+            host = own_host.get();
         }
-        partials.alloc(npart * sizeof(double));
-        st_in.alloc(sizeof(RhsState) * n);
-        st_out.alloc(sizeof(RhsState) * n);
-        mirror.alloc(sizeof(RhsState) * n * kRing);
-        hinit.alloc(sizeof(RhsState) * n);
-        hread.alloc(sizeof(RhsState) * n);
-        for (auto &e : ring_ev) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ring_ev = host->ring;
+        // the Krylov fields start at zero (a workspace holds whatever its last user left)
         std::vector<Spinor> all = {r.f, rh.f, p.f, v.f, s.f, t.f, tmp.f};
         for (auto &f : all) WL_HIP(launch_zero(f, g, n, ctx->stream));
-    }
-    ~EoCore() {
-        for (auto &e : ring_ev)
-            if (e) (void)hipEventDestroy(e);
     }
     // use another gauge field of the same shape
     void bind(const wilson_gauge *gauge) {
@@ -100,12 +137,7 @@ class EoCore {
         G = gauge;
     }
 
-    size_t footprint() const {
-        size_t b = 0;
-        for (const FieldBuf *f : {&b_e, &b_o, &x_e, &x_o, &bp, &r64, &tmp64, &r, &rh, &p, &v, &s, &t, &tmp, &rf, &xin})
-            b += f->buf.size();
-        return b + partials.size() + st_in.size() + st_out.size() + bstate.size();
-    }
+    size_t footprint() const { return bytes; }
 
     Spinor V(Spinor f) const {
         if (!f.data) return f;
@@ -119,11 +151,11 @@ class EoCore {
     void select(int first, int count) { k0 = first; nk = count; }
     void select_all() { k0 = 0; nk = nrhs; }
 
-    RhsState *sin() const { return st_in.as<RhsState>(); }
-    RhsState *sout() const { return st_out.as<RhsState>(); }
-    RhsState *mirror_dev(int slot) const { return reinterpret_cast<RhsState *>(mirror.dev()) + (size_t)slot * nrhs; }
-    RhsState *mirror_host(int slot) const { return reinterpret_cast<RhsState *>(mirror.host()) + (size_t)slot * nrhs; }
-    double *part() const { return partials.as<double>(); }
+    RhsState *sin() const { return st_in; }
+    RhsState *sout() const { return st_out; }
+    RhsState *mirror_dev(int slot) const { return reinterpret_cast<RhsState *>(host->mirror.dev()) + (size_t)slot * nrhs; }
+    RhsState *mirror_host(int slot) const { return reinterpret_cast<RhsState *>(host->mirror.host()) + (size_t)slot * nrhs; }
+    double *part() const { return partials; }
     const void *links(int prec) const { return G->links(prec == P64 ? P64 : GP); }
     int lprec(int prec) const { return prec == P64 ? P64 : GP; }
 
@@ -205,7 +237,7 @@ class EoCore {
         a.g = g;
         a.s = nk;
         a.partials = part();
-        a.bs = bstate.as<BlockState>();
+        a.bs = bstate;
         a.state = S(st);
         a.mirror = mir ? mir + k0 : nullptr;
         return a;
@@ -237,15 +269,15 @@ class EoCore {
     // host <-> device copies of the states of the selected range
     void upload_states(RhsState *dst, const std::vector<RhsState> &h) {
         WL_HIP(hipStreamSynchronize(ctx->stream));  // hinit may still be the source of a copy
-        std::memcpy(hinit.host(), h.data(), sizeof(RhsState) * nk);
-        WL_HIP(hipMemcpyAsync(S(dst), hinit.host(), sizeof(RhsState) * nk, hipMemcpyHostToDevice, ctx->stream));
+        std::memcpy(host->hinit.host(), h.data(), sizeof(RhsState) * nk);
+        WL_HIP(hipMemcpyAsync(S(dst), host->hinit.host(), sizeof(RhsState) * nk, hipMemcpyHostToDevice, ctx->stream));
     }
     std::vector<RhsState> read_states(RhsState *src) {
-        WL_HIP(hipMemcpyAsync(hread.host(), S(src), sizeof(RhsState) * nk, hipMemcpyDeviceToHost, ctx->stream));
+        WL_HIP(hipMemcpyAsync(host->hread.host(), S(src), sizeof(RhsState) * nk, hipMemcpyDeviceToHost, ctx->stream));
         WL_HIP(hipStreamSynchronize(ctx->stream));
         ctx->drain_timing();
         std::vector<RhsState> h(nk);
-        std::memcpy(h.data(), hread.host(), sizeof(RhsState) * nk);
+        std::memcpy(h.data(), host->hread.host(), sizeof(RhsState) * nk);
         return h;
     }
 
@@ -516,18 +548,8 @@ static std::shared_ptr<EoCore> get_core(wilson_ctx *ctx, const wilson_gauge *G, 
 }
 
 size_t solve_footprint(const Geom &g, int nrhs, const SolveParams &p) {
-    const int P = inner_prec(p.precision), PX = P == P16 ? P32 : P;
-    const bool mixed = p.precision != WILSON_FP64;
-    auto fb = [&](int prec) { return (size_t)nrhs * spinor_field_bytes(prec, g); };
-    size_t b = 5 * fb(P64) + 7 * fb(P);
-    if (mixed) b += 2 * fb(P64) + fb(P) + fb(PX);
-    size_t npart = partials_doubles(g, nrhs);
-    if (p.method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) {
-        npart = std::max(npart, block_partials_doubles(g));
-        b += sizeof(BlockState);
-    }
-    b += npart * sizeof(double) + 2 * sizeof(RhsState) * nrhs;
-    return b;
+    EoMem m;
+    return m.carve(nullptr, g, nrhs, p.precision, p.method);
 }
 
 int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const double *b_canon, int nrhs,
@@ -535,7 +557,11 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t hop0 = ctx->hop_launch_count;
     const double bytes0 = ctx->bytes_issued, flops0 = ctx->flops_issued;
-    auto core = get_core(ctx, G, nrhs, prm);
+    // a caller's region holds the device buffers of this call only (built per call, with
+    // the context's host resources); otherwise a cached workspace of the context
+    auto core = prm.workspace ? std::make_shared<EoCore>(ctx, G, nrhs, prm.precision, prm.method, prm.workspace,
+                                                         prm.workspace_bytes, &ctx->lend)
+                              : get_core(ctx, G, nrhs, prm);
     EoCore &C = *core;
     const Geom &g = C.g;
     C.select(0, nrhs);
@@ -928,7 +954,8 @@ class BatchEngine {
 
     BatchEngine(wilson_ctx *c, const wilson_gauge *g, int nslots, const SolveParams &p)
         : ctx(c), G(g), prm(p), n(nslots), slots(nslots) {
-        C = std::make_unique<EoCore>(c, g, nslots, p.precision, p.method);
+        // a caller's workspace holds the batch's device buffers until the batch is destroyed
+        C = std::make_unique<EoCore>(c, g, nslots, p.precision, p.method, p.workspace, p.workspace_bytes);
         C->kappa.assign(nslots, 0.0);
         delta = p.inner_tol > 0 ? p.inner_tol : (C->P == P32 ? 1e-5 : (C->P == P16 ? 1e-2 : 0.0));
         std::vector<RhsState> h(n);

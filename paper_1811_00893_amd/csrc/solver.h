@@ -19,10 +19,39 @@
 
 namespace wl {
 
+// Bump allocator over one device region: buffers at increasing 256-byte aligned offsets.
+// With no base it only measures (the pointers it hands out are then null).
+struct Arena {
+    char *base = nullptr;
+    size_t used = 0;
+    void *take(size_t bytes) {
+        used = (used + 255) & ~size_t(255);
+        void *p = base ? base + used : nullptr;
+        used += bytes;
+        return p;
+    }
+};
+
 struct FieldBuf {
-    DevBuf buf;
+    DevBuf buf;   // owning storage (make); empty when the field is placed in an arena
     Spinor f;
     void make(int prec, const Geom &g, int nrhs);
+    void place(int prec, const Geom &g, int nrhs, Arena &A);
+};
+
+// Device memory of one even-odd problem with nrhs right-hand sides: every field, the
+// reduction partials and the per-RHS states, carved in a fixed order out of one region
+// (the library's own allocation or a caller's workspace).
+struct EoMem {
+    FieldBuf b_e, b_o, x_e, x_o, bp;          // FP64 problem
+    FieldBuf r64, tmp64;                      // FP64 outer residual (mixed only)
+    FieldBuf r, rh, p, v, s, t, tmp, rf, xin; // inner Krylov fields
+    double *partials = nullptr;
+    RhsState *st_in = nullptr, *st_out = nullptr;
+    BlockState *bstate = nullptr;             // block BiCGStab only
+    size_t bytes = 0;                         // size of the region
+    // places every buffer from base (nullptr: sizes only); returns the region's size
+    size_t carve(char *base, const Geom &g, int nrhs, int precision, int method);
 };
 
 struct SolveParams {
@@ -34,6 +63,8 @@ struct SolveParams {
     bool use_x0 = false;
     int poll_every = 1;
     bool reliable = false;  // mixed precision: reliable updates instead of defect correction
+    void *workspace = nullptr;    // device region for every buffer of the solve (null: the library's)
+    size_t workspace_bytes = 0;
 };
 
 // Solves for nrhs right-hand sides given in canonical layout on the device.
