@@ -130,10 +130,10 @@ __global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a,
     double red[3] = {0.0, 0.0, 0.0};
     blas_math<OP, CPE, R, R>(st, o, red);
     if (valid) {
-        if constexpr (S::ST & SA) st_elem<P, R>(const_cast<char *>(splane(a.a.data, plane, stride)), off, o.a);
-        if constexpr (S::ST & SB) st_elem<P, R>(const_cast<char *>(splane(a.b.data, plane, stride)), off, o.b);
-        if constexpr (S::ST & SC) st_elem<P, R>(const_cast<char *>(splane(a.c.data, plane, stride)), off, o.c);
-        if constexpr (S::ST & SX) st_elem<P, R>(const_cast<char *>(splane(a.x.data, plane, stride)), off, o.x);
+        if constexpr (S::ST & SA) st_elem<P, R>(const_cast<gchar *>(splane(a.a.data, plane, stride)), off, o.a);
+        if constexpr (S::ST & SB) st_elem<P, R>(const_cast<gchar *>(splane(a.b.data, plane, stride)), off, o.b);
+        if constexpr (S::ST & SC) st_elem<P, R>(const_cast<gchar *>(splane(a.c.data, plane, stride)), off, o.c);
+        if constexpr (S::ST & SX) st_elem<P, R>(const_cast<gchar *>(splane(a.x.data, plane, stride)), off, o.x);
     } else {
         red[0] = red[1] = red[2] = 0.0;
     }

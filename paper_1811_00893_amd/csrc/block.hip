@@ -27,22 +27,23 @@ using dcx = Cx<double>;
 __device__ __forceinline__ bool block_running(const BlockArgs &a) { return a.state[0].phase == PH_RUN; }
 
 // plane address shared by the whole wavefront (kept in scalar registers)
-__device__ __forceinline__ const dvec2 *fplane(const void *base, int plane, int stride) {
-    return reinterpret_cast<const dvec2 *>(splane(base, plane, stride));
+typedef const WL_GLOBAL dvec2 *gdvec2p;
+__device__ __forceinline__ gdvec2p fplane(const void *base, int plane, int stride) {
+    return reinterpret_cast<gdvec2p>(splane(base, plane, stride));
 }
 // plane address that differs between the lanes of a wavefront (no scalar promotion)
-__device__ __forceinline__ const dvec2 *fplane_lane(const void *base, int plane, int stride) {
-    return reinterpret_cast<const dvec2 *>(static_cast<const char *>(base) + (size_t)plane * stride * 16u);
+__device__ __forceinline__ gdvec2p fplane_lane(const void *base, int plane, int stride) {
+    return gptr(reinterpret_cast<const dvec2 *>(static_cast<const char *>(base) + (size_t)plane * stride * 16u));
 }
-__device__ __forceinline__ dcx ldc(const dvec2 *p, int i) {
+__device__ __forceinline__ dcx ldc(gdvec2p p, int i) {
     const dvec2 v = p[i];
     return {v.x, v.y};
 }
-__device__ __forceinline__ void stc(const dvec2 *p, int i, dcx v) {
+__device__ __forceinline__ void stc(gdvec2p p, int i, dcx v) {
     dvec2 w;
     w.x = v.re;
     w.y = v.im;
-    const_cast<dvec2 *>(p)[i] = w;
+    const_cast<WL_GLOBAL dvec2 *>(p)[i] = w;
 }
 
 // ---------------------------------------------------------------------------------
@@ -443,7 +444,7 @@ __global__ void __launch_bounds__(kUpdBlock) block_update_kernel(const BlockArgs
                 } else if constexpr (OP == BU_XR) {
                     const dcx sj = ldc(fplane(a.b.data, j * 12 + c, stride), site);
                     const dcx tj = ldc(fplane(a.d.data, j * 12 + c, stride), site);
-                    const dvec2 *xp = fplane(a.x.data, j * 12 + c, stride);
+                    gdvec2p xp = fplane(a.x.data, j * 12 + c, stride);
                     const dcx x = ldc(xp, site);
                     stc(xp, site, cadd(x, cadd(acc, cmul(omega, sj))));
                     const dcx r = csub(sj, cmul(omega, tj));

@@ -73,7 +73,7 @@ __device__ void store36(void *base, int prec, int blk, int stride, int i, const 
             dvec2 v;
             v.x = m[2 * e];
             v.y = m[2 * e + 1];
-            *reinterpret_cast<dvec2 *>(const_cast<char *>(splane(base, blk * 18 + e, stride)) + off) = v;
+            *reinterpret_cast<WL_GLOBAL dvec2 *>(const_cast<gchar *>(splane(base, blk * 18 + e, stride)) + off) = v;
         }
     } else {
         for (int e = 0; e < 9; e++) {
@@ -82,7 +82,7 @@ __device__ void store36(void *base, int prec, int blk, int stride, int i, const 
             v.y = (float)m[4 * e + 1];
             v.z = (float)m[4 * e + 2];
             v.w = (float)m[4 * e + 3];
-            *reinterpret_cast<fvec4 *>(const_cast<char *>(splane(base, blk * 9 + e, stride)) + off) = v;
+            *reinterpret_cast<WL_GLOBAL fvec4 *>(const_cast<gchar *>(splane(base, blk * 9 + e, stride)) + off) = v;
         }
     }
 }

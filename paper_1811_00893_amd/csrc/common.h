@@ -173,6 +173,7 @@ struct LaunchCfg {
     int shx = 0;       // 1: x/y neighbours shuffled from the lanes that loaded them (RPT 1)
     int dsplit = 0;    // 1: five waves per 64-site tile, wave 1 + mu on direction mu (block 320, RPT 1)
     int ldsl = 0;      // 1: with wsplit, the tile's links loaded once into LDS for all waves of the block
+    int tm = 0;        // >= 1: each block marches its segment of the (x,y,z) slices through tm t-slices (every second one)
 };
 
 // ---- block BiCGStab (several right-hand sides of one matrix share one Krylov space) ----

@@ -64,6 +64,23 @@ typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef _Float16 hvec4 __attribute__((ext_vector_type(4)));
 typedef _Float16 hvec8 __attribute__((ext_vector_type(8)));
 
+// Fields in device memory are addressed through pointers of the global address space, so
+// their loads and stores are global_load / global_store.  Through a generic pointer they
+// would be flat accesses, which also count against the counter of LDS and scalar loads:
+// every wait for an LDS read or a kernel argument would then also wait for all memory
+// loads in flight.  (A generic pointer loses its address space in the integer round trip
+// of uniform_ptr below, and a field pointer read from a kernel's argument struct has none.)
+#define WL_GLOBAL __attribute__((address_space(1)))
+typedef WL_GLOBAL char gchar;
+template <typename T>
+__device__ __forceinline__ const WL_GLOBAL T *gptr(const T *p) {
+    return (const WL_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ WL_GLOBAL T *gptr_w(T *p) {
+    return (WL_GLOBAL T *)p;
+}
+
 template <int P>
 struct SpinorPack {
     static constexpr int CPE = P == P64 ? 1 : (P == P32 ? 2 : 4);  // complex per element
@@ -88,49 +105,49 @@ __host__ __device__ constexpr unsigned link_elem_bytes(int prec) { return prec =
 // belong to different fields or parities takes them from blockIdx, not from the lane).
 // Without it the compiler folds the lane offset into the base first and then adds each
 // plane's offset with a 64-bit per-lane multiply-add, instead of one scalar base per plane.
-__device__ __forceinline__ const char *uniform_ptr(const char *p) {
+__device__ __forceinline__ const gchar *uniform_ptr(const char *p) {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return reinterpret_cast<const char *>(((uint64_t)hi << 32) | lo);
+    return reinterpret_cast<const gchar *>(((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ const char *splane(const void *base, int plane, int stride) {
+__device__ __forceinline__ const gchar *splane(const void *base, int plane, int stride) {
     return uniform_ptr(static_cast<const char *>(base) + (size_t)plane * stride * 16u);
 }
 template <int P>
-__device__ __forceinline__ const char *lplane(const void *base, int plane, int stride) {
+__device__ __forceinline__ const gchar *lplane(const void *base, int plane, int stride) {
     return uniform_ptr(static_cast<const char *>(base) + (size_t)plane * stride * LinkPack<P>::EB);
 }
 
 template <int P, typename R>
-__device__ __forceinline__ void ld_elem(Cx<R> *o, const char *plane, unsigned off) {
+__device__ __forceinline__ void ld_elem(Cx<R> *o, const gchar *plane, unsigned off) {
     if constexpr (P == P64) {
-        const dvec2 v = *reinterpret_cast<const dvec2 *>(plane + off);
+        const dvec2 v = *reinterpret_cast<const WL_GLOBAL dvec2 *>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
     } else if constexpr (P == P32) {
-        const fvec4 v = *reinterpret_cast<const fvec4 *>(plane + off);
+        const fvec4 v = *reinterpret_cast<const WL_GLOBAL fvec4 *>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
         o[1] = {(R)v.z, (R)v.w};
     } else {
-        const hvec8 v = *reinterpret_cast<const hvec8 *>(plane + off);
+        const hvec8 v = *reinterpret_cast<const WL_GLOBAL hvec8 *>(plane + off);
 #pragma unroll
         for (int k = 0; k < 4; k++) o[k] = {(R)(float)v[2 * k], (R)(float)v[2 * k + 1]};
     }
 }
 template <int P, typename R>
-__device__ __forceinline__ void st_elem(char *plane, unsigned off, const Cx<R> *x) {
+__device__ __forceinline__ void st_elem(gchar *plane, unsigned off, const Cx<R> *x) {
     if constexpr (P == P64) {
         dvec2 v;
         v.x = (double)x[0].re;
         v.y = (double)x[0].im;
-        *reinterpret_cast<dvec2 *>(plane + off) = v;
+        *reinterpret_cast<WL_GLOBAL dvec2 *>(plane + off) = v;
     } else if constexpr (P == P32) {
         fvec4 v;
         v.x = (float)x[0].re;
         v.y = (float)x[0].im;
         v.z = (float)x[1].re;
         v.w = (float)x[1].im;
-        *reinterpret_cast<fvec4 *>(plane + off) = v;
+        *reinterpret_cast<WL_GLOBAL fvec4 *>(plane + off) = v;
     } else {
         hvec8 v;
 #pragma unroll
@@ -138,19 +155,19 @@ __device__ __forceinline__ void st_elem(char *plane, unsigned off, const Cx<R> *
             v[2 * k] = (_Float16)(float)x[k].re;
             v[2 * k + 1] = (_Float16)(float)x[k].im;
         }
-        *reinterpret_cast<hvec8 *>(plane + off) = v;
+        *reinterpret_cast<WL_GLOBAL hvec8 *>(plane + off) = v;
     }
 }
 // link element.  NT (non-temporal) when a launch reads each link once, so links do not
 // evict spinors from L2; ordinary loads when several right-hand-side groups read the same
 // links one after another and must find them in L2.
 template <typename T, bool NT>
-__device__ __forceinline__ T ld_maybe_nt(const char *p) {
-    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
-    else return *reinterpret_cast<const T *>(p);
+__device__ __forceinline__ T ld_maybe_nt(const gchar *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const WL_GLOBAL T *>(p));
+    else return *reinterpret_cast<const WL_GLOBAL T *>(p);
 }
 template <int P, typename R, bool NT>
-__device__ __forceinline__ void ld_link_elem(Cx<R> *o, const char *plane, unsigned off) {
+__device__ __forceinline__ void ld_link_elem(Cx<R> *o, const gchar *plane, unsigned off) {
     if constexpr (P == P64) {
         const dvec2 v = ld_maybe_nt<dvec2, NT>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
@@ -164,27 +181,43 @@ __device__ __forceinline__ void ld_link_elem(Cx<R> *o, const char *plane, unsign
         o[1] = {(R)(float)v[2], (R)(float)v[3]};
     }
 }
+// the same element from a block's LDS copy of the links (a __shared__ buffer)
 template <int P, typename R>
-__device__ __forceinline__ void st_link_elem(char *plane, unsigned off, const Cx<R> *x) {
+__device__ __forceinline__ void ld_link_elem_lds(Cx<R> *o, const char *lds, unsigned off) {
+    if constexpr (P == P64) {
+        const dvec2 v = *reinterpret_cast<const dvec2 *>(lds + off);
+        o[0] = {(R)v.x, (R)v.y};
+    } else if constexpr (P == P32) {
+        const fvec4 v = *reinterpret_cast<const fvec4 *>(lds + off);
+        o[0] = {(R)v.x, (R)v.y};
+        o[1] = {(R)v.z, (R)v.w};
+    } else {
+        const hvec4 v = *reinterpret_cast<const hvec4 *>(lds + off);
+        o[0] = {(R)(float)v[0], (R)(float)v[1]};
+        o[1] = {(R)(float)v[2], (R)(float)v[3]};
+    }
+}
+template <int P, typename R>
+__device__ __forceinline__ void st_link_elem(gchar *plane, unsigned off, const Cx<R> *x) {
     if constexpr (P == P64) {
         dvec2 v;
         v.x = (double)x[0].re;
         v.y = (double)x[0].im;
-        *reinterpret_cast<dvec2 *>(plane + off) = v;
+        *reinterpret_cast<WL_GLOBAL dvec2 *>(plane + off) = v;
     } else if constexpr (P == P32) {
         fvec4 v;
         v.x = (float)x[0].re;
         v.y = (float)x[0].im;
         v.z = (float)x[1].re;
         v.w = (float)x[1].im;
-        *reinterpret_cast<fvec4 *>(plane + off) = v;
+        *reinterpret_cast<WL_GLOBAL fvec4 *>(plane + off) = v;
     } else {
         hvec4 v;
         v[0] = (_Float16)(float)x[0].re;
         v[1] = (_Float16)(float)x[0].im;
         v[2] = (_Float16)(float)x[1].re;
         v[3] = (_Float16)(float)x[1].im;
-        *reinterpret_cast<hvec4 *>(plane + off) = v;
+        *reinterpret_cast<WL_GLOBAL hvec4 *>(plane + off) = v;
     }
 }
 
@@ -196,7 +229,7 @@ __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int s
 #pragma unroll
     for (int e = 0; e < NEL; e++) ld_elem<P, R>(&v[e * CPE], splane(f.data, r * NEL + e, stride), off);
     if constexpr (P == P16) {
-        const R s = (R)f.scale[(size_t)r * stride + i];
+        const R s = (R)gptr(f.scale)[(size_t)r * stride + i];
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] = cscale(v[c], s);
     }
@@ -218,12 +251,12 @@ __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, i
             q[c] = s > 0.f ? Cx<float>{(float)v[c].re / sd, (float)v[c].im / sd} : Cx<float>{0.f, 0.f};
 #pragma unroll
         for (int e = 0; e < NEL; e++)
-            st_elem<P, float>(const_cast<char *>(splane(f.data, r * NEL + e, stride)), off, &q[e * CPE]);
-        f.scale[(size_t)r * stride + i] = s;
+            st_elem<P, float>(const_cast<gchar *>(splane(f.data, r * NEL + e, stride)), off, &q[e * CPE]);
+        gptr_w(f.scale)[(size_t)r * stride + i] = s;
     } else {
 #pragma unroll
         for (int e = 0; e < NEL; e++)
-            st_elem<P, R>(const_cast<char *>(splane(f.data, r * NEL + e, stride)), off, &v[e * CPE]);
+            st_elem<P, R>(const_cast<gchar *>(splane(f.data, r * NEL + e, stride)), off, &v[e * CPE]);
     }
 }
 
@@ -247,13 +280,13 @@ __device__ __forceinline__ void clov_load_block(R (&m)[36], const void *base, in
     const unsigned off = (unsigned)i * 16u;
 #pragma unroll
     for (int e = 0; e < EPB; e++) {
-        const char *pl = splane(base, blk * EPB + e, stride);
+        const gchar *pl = splane(base, blk * EPB + e, stride);
         if constexpr (P == P64) {
-            const dvec2 v = *reinterpret_cast<const dvec2 *>(pl + off);
+            const dvec2 v = *reinterpret_cast<const WL_GLOBAL dvec2 *>(pl + off);
             m[2 * e] = (R)v.x;
             m[2 * e + 1] = (R)v.y;
         } else {
-            const fvec4 v = *reinterpret_cast<const fvec4 *>(pl + off);
+            const fvec4 v = *reinterpret_cast<const WL_GLOBAL fvec4 *>(pl + off);
             m[4 * e] = (R)v.x;
             m[4 * e + 1] = (R)v.y;
             m[4 * e + 2] = (R)v.z;

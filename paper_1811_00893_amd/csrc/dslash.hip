@@ -12,7 +12,11 @@ hipError_t launch_hop_r(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
 bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
     if (c.dsplit)  // one RHS per block, five waves, memory-order tiles of 64 sites
         return c.dsplit == 1 && c.block == 320 && c.rpt == 1 && !c.shx && !c.wsplit && c.zblk == 0 && c.lds_kb == 0 &&
-               !c.ldsl;
+               !c.ldsl && !c.tm;
+    if (c.tm) {  // t-marching: whole t-chunks, segments of at least one wavefront per slice, no clover
+        if (c.tm < 1 || a.g.L[3] % (2 * c.tm) != 0 || a.g.st < 64) return false;
+        if (c.zblk != 0 || c.lds_kb != 0 || a.clov_mode != CLV_NONE) return false;
+    }
     if (c.ldsl) {  // links in LDS: wave split, one or two RHS per lane, no clover epilogue
         if (c.ldsl != 1 || !c.wsplit || c.lds_kb != 0 || c.rpt > 2 || (c.shx && c.rpt != 1)) return false;
         if (a.clov_mode != CLV_NONE || (a.gprec == P64 && a.recon == 18)) return false;
@@ -37,6 +41,7 @@ bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
 // Number of site tiles of a launch (the row length of the partial sums it writes).
 int hop_nblocks(const HopArgs &a, const LaunchCfg &c) {
     const int tile = c.wsplit || c.dsplit ? 64 : c.block;
+    if (c.tm) return (a.g.st + tile - 1) / tile * (a.g.L[3] / c.tm);
     return (a.g.Vh + tile - 1) / tile;
 }
 

@@ -112,7 +112,8 @@ __device__ __forceinline__ void proj_in(const Cx<real_t<SP>> (&comp)[12], real_t
 // SRC selects where the neighbour comes from: 0 = loaded here from the input field;
 // 1 = its projected half spinors given in H.  LL: the link comes from the block's LDS copy
 // `ll` (see stage_links) instead of global memory.
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD, int SRC = 0, bool LL = false>
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD, int SRC = 0, bool LL = false,
+          int BAR = -1>
 __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
                                         int r0, int nbr, int link_par, int link_site, real_t<SP> sgn, int stride,
                                         const Cx<real_t<SP>> (*H)[2][3] = nullptr, const char *ll = nullptr) {
@@ -127,7 +128,7 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
             const unsigned lane = threadIdx.x & 63u;
 #pragma unroll
             for (int e = 0; e < NL; e++)
-                ld_link_elem<GP, R, false>(&ue[e * CPL], ll, ((unsigned)(d * NL + e) * 64u + lane) * LinkPack<GP>::EB);
+                ld_link_elem_lds<GP, R>(&ue[e * CPL], ll, ((unsigned)(d * NL + e) * 64u + lane) * LinkPack<GP>::EB);
         } else {
             const unsigned loff = (unsigned)link_site * LinkPack<GP>::EB;
 #pragma unroll
@@ -168,7 +169,7 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
                     for (int k = 0; k < CPE; k++) comp[e * CPE + k] = {R(0), R(0)};
             }
             R sc = R(1);
-            if constexpr (SP == P16) sc = (R)a.in.scale[(size_t)(r0 + r) * stride + nbr];
+            if constexpr (SP == P16) sc = (R)gptr(a.in.scale)[(size_t)(r0 + r) * stride + nbr];
             proj_in<SP, MU, FWD, G5>(comp, sc, h);
         } else {
 #pragma unroll
@@ -195,7 +196,8 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
     // and a barrier after each group keeps later gathers from being hoisted into it (all
     // eight directions in flight need more registers than the budget; one direction at a
     // time measured 1.5 % slower in FP64)
-    if constexpr ((MU == 1 || MU == 3) && !FWD) __builtin_amdgcn_sched_barrier(0);
+    // (BAR 0 / 1: no barrier / a barrier after this direction, for other orders)
+    if constexpr (BAR == 1 || (BAR < 0 && (MU == 1 || MU == 3) && !FWD)) __builtin_amdgcn_sched_barrier(0);
 }
 
 // One output site i (all RPT right-hand sides of this lane): gather, project, multiply,
@@ -217,7 +219,7 @@ __device__ __forceinline__ void load_raw(Cx<real_t<SP>> (&v)[RPT][12], real_t<SP
 #pragma unroll
         for (int e = 0; e < NEL; e++)
             ld_elem<SP, R>(&v[r][e * CPE], splane(a.in.data, (r0 + r) * NEL + e, stride), (unsigned)j * 16u);
-        if constexpr (SP == P16) vs[r] = (R)a.in.scale[(size_t)(r0 + r) * stride + j];
+        if constexpr (SP == P16) vs[r] = (R)gptr(a.in.scale)[(size_t)(r0 + r) * stride + j];
         else vs[r] = R(1);
     }
 }
@@ -265,9 +267,9 @@ __device__ __forceinline__ void lane_nbr(Cx<real_t<SP>> (&H)[RPT][2][3], const C
 template <int SP, bool CLV, int PRE>
 __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, int rhs,
                                            const Cx<real_t<SP>> (&acc)[4][3], Cx<real_t<SP>> (&yv)[12],
-                                           Cx<real_t<SP>> (&zv)[12], Cx<real_t<SP>> (&wv)[12], double (&red)[3]) {
+                                           Cx<real_t<SP>> (&zv)[12], Cx<real_t<SP>> (&wv)[12], double (&red)[3],
+                                           int stride) {
     using R = real_t<SP>;
-    const int stride = a.g.stride;
     constexpr int CP = SP == P64 ? P64 : P32;  // storage precision of clover blocks
     const R cH = (R)a.cH[rhs];
     Cx<R> o[12];
@@ -325,7 +327,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
 // d = w, w + nw, ... (lane l for site l of the tile), and everyone reads it from there.
 // Every wave of the block calls this (it holds a block barrier).
 template <int GP, int NE>
-__device__ __forceinline__ void stage_links(char *ll, const HopArgs &a, int par, const int (&lsite)[8]) {
+__device__ __forceinline__ void stage_links(char *ll, const HopArgs &a, int par, const int (&lsite)[8], int stride) {
     constexpr int NL = LinkElems<GP, NE>::N;
     constexpr unsigned EB = LinkPack<GP>::EB;
     const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
@@ -334,10 +336,12 @@ __device__ __forceinline__ void stage_links(char *ll, const HopArgs &a, int par,
         const int site = lsite[d];
 #pragma unroll
         for (int e = 0; e < NL; e++) {
-            const char *src = lplane<GP>(a.gauge, (lpar * 4 + mu) * NL + e, a.g.stride) + (unsigned)site * EB;
+            const gchar *src = lplane<GP>(a.gauge, (lpar * 4 + mu) * NL + e, stride) + (unsigned)site * EB;
             char *dst = ll + ((unsigned)(d * NL + e) * 64u + lane) * EB;
-            if constexpr (EB == 16) *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
-            else *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+            typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+            typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+            if constexpr (EB == 16) *reinterpret_cast<u32x4 *>(dst) = *reinterpret_cast<const WL_GLOBAL u32x4 *>(src);
+            else *reinterpret_cast<u32x2 *>(dst) = *reinterpret_cast<const WL_GLOBAL u32x2 *>(src);
         }
     }
     __syncthreads();
@@ -365,7 +369,7 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     if constexpr (LL) {
         __shared__ __align__(16) char ll_buf[8 * LinkElems<GP, NE>::N * 64 * LinkPack<GP>::EB];
         const int lsite[8] = {i, xm, i, ym, i, zm, i, tm};
-        stage_links<GP, NE>(ll_buf, a, par, lsite);
+        stage_links<GP, NE>(ll_buf, a, par, lsite, stride);
         ll = ll_buf;
         bool any = false;
 #pragma unroll
@@ -414,7 +418,7 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     for (int r = 0; r < RPT; r++) {
         if (RPT > 1 && !act[r]) continue;
         Cx<R> yv[12], zv[12], wv[12];
-        hop_finish<SP, CLV, 0>(a, i, valid, r0 + r, acc[r], yv, zv, wv, red[r]);
+        hop_finish<SP, CLV, 0>(a, i, valid, r0 + r, acc[r], yv, zv, wv, red[r], stride);
     }
 }
 
@@ -496,6 +500,222 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     }
 }
 
+// t-marching: the sites of a launch are cut into segments of `tile` consecutive positions
+// of the (x, y, z) slices (a position p is the checkerboard index within a slice; the site
+// of slice t is i = t * st + p), and a block marches one segment through nt t-slices of
+// one parity of t: t = t0, t0 + 2, ..., t0 + 2 (nt - 1).  In the Dirac basis a t-hop reads
+// one spin half of its neighbour, and the input at (t + 1, p) is the forward t-neighbour of
+// output (t, p) and the backward t-neighbour of output (t + 2, p), the block's next step:
+// it is loaded once, its forward half used at once and its projected backward half kept
+// in registers for the next step.  The two blocks of a segment and 2 nt slices (t0 even
+// and odd) load each input of those slices once between them, plus one half-slice of halo
+// each; the plain kernel loads the two t-neighbour halves of every site separately, 2 Lz
+// planes apart in memory and far beyond the L2 of an XCD.  Blocks are ordered t-chunk
+// major, then segment, then the slice parity, so an XCD's contiguous range of blocks
+// covers neighbouring segments (the z-neighbours) of the same slices.  Links come from
+// global memory, or (LL, with the wave split) are staged in LDS per step for all waves.
+// No clover epilogue.
+// Register budget of the marching kernels: the loop keeps one projected half per RHS and
+// the per-step plane bases beyond the plain kernel's (FP64: 2 waves per SIMD; FP32/FP16:
+// 3 up to two RHS per lane, 2 beyond).
+template <int SP, int RPT>
+struct TmOcc {
+    static constexpr int value = SP == P64 ? 2 : (RPT <= 2 ? 3 : 2);
+};
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool LL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TmOcc<SP, RPT>::value)))
+hop_kernel_tm(const HopArgs a, int xcd_remap, int nt, int wsplit) {
+    using R = real_t<SP>;
+    const Geom &g = a.g;
+    const int stride = g.stride;
+    const int par = a.par, opar = 1 - par;
+    const int ngroups = a.nrhs / RPT;
+    const int nw = (int)blockDim.x >> 6;
+    const int bpt = wsplit ? ngroups / nw : ngroups;  // blocks per tile
+    const int tile = wsplit ? 64 : (int)blockDim.x;
+    const int nseg = (g.st + tile - 1) / tile;
+    const int lb = xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tid = lb / bpt;  // tile: (t-chunk, segment, slice parity), the last fastest
+    const int q = tid & 1, cs = tid >> 1;
+    const int chunk = cs / nseg, seg = cs - chunk * nseg;
+    int r0, pos;
+    if (wsplit) {
+        r0 = __builtin_amdgcn_readfirstlane(((lb - tid * bpt) * nw + ((int)threadIdx.x >> 6)) * RPT);
+        pos = seg * 64 + ((int)threadIdx.x & 63);
+    } else {
+        r0 = (lb - tid * bpt) * RPT;
+        pos = seg * tile + (int)threadIdx.x;
+    }
+    const bool valid = pos < g.st;
+    const int p = valid ? pos : g.st - 1;  // ragged last segment: computed, not stored
+    bool act[RPT];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        act[r] = (r0 + r < a.nrhs) && (a.state == nullptr || (a.state[r0 + r].phase & a.run_mask));
+        any |= act[r];
+    }
+    if (!any && !LL) return;  // uniform over the block (the wave with wsplit)
+
+    const int Lt = g.L[3];
+    const int t0 = chunk * 2 * nt + q;
+    double red[RPT][3];
+#pragma unroll
+    for (int r = 0; r < RPT; r++) red[r][0] = red[r][1] = red[r][2] = 0.0;
+
+    // the projected backward half of the input at (t0 - 1, p), for the first step
+    Cx<R> pb[RPT][2][3];
+    {
+        Cx<R> v[RPT][12];
+        R vs[RPT];
+        load_raw<SP, RPT>(v, vs, a, act, r0, (t0 == 0 ? Lt - 1 : t0 - 1) * g.st + p, stride);
+#pragma unroll
+        for (int r = 0; r < RPT; r++) proj_in<SP, 3, false, G5>(v[r], vs[r], pb[r]);
+    }
+    const char *ll = nullptr;
+    __shared__ __align__(16) char ll_buf[LL ? 8 * LinkElems<GP, NE>::N * 64 * LinkPack<GP>::EB : 16];
+    if constexpr (LL) ll = ll_buf;
+
+    for (int j = 0; j < nt; j++) {
+        // the plane stride, opaque to the compiler on every step: the forty-odd plane base
+        // addresses derived from it are then formed in scalar registers per step instead of
+        // being hoisted out of the loop (which spills the scalar registers)
+        int ls = stride;
+        asm volatile("" : "+s"(ls));
+
+        const int t = t0 + 2 * j;
+        const int i = t * g.st + p;
+        const SiteXY c = cb_coords(g, i, par);
+        const int row = i - c.xh;
+        const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
+        const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
+        const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
+        const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
+        const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
+        const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
+        const int tp = (t == Lt - 1) ? p : i + g.st;
+        const int tm = (t == 0) ? (Lt - 1) * g.st + p : i - g.st;
+        if constexpr (LL) {
+            if (j > 0) __syncthreads();  // every wave has read the previous step's links
+            const int lsite[8] = {i, xm, i, ym, i, zm, i, tm};
+            stage_links<GP, NE>(ll_buf, a, par, lsite, ls);
+        }
+        if (!any) continue;  // (LL) this wave's RHS group has finished; it only helps staging
+
+        Cx<R> acc[RPT][4][3];
+#pragma unroll
+        for (int r = 0; r < RPT; r++)
+#pragma unroll
+            for (int s_ = 0; s_ < 4; s_++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) acc[r][s_][k] = {R(0), R(0)};
+        const R one = R(1);
+        if constexpr (SHX) {
+            Cx<R> C[RPT][12];
+            R Cs[RPT];
+            load_raw<SP, RPT>(C, Cs, a, act, r0, i, ls);
+            Cx<R> H[RPT][2][3];
+            lane_nbr<SP, RPT, 0, true, G5>(H, C, Cs, a, act, r0, i, xp, ls);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 1, LL>(acc, a, act, r0, xp, par, i, one, ls, H, ll);
+            lane_nbr<SP, RPT, 0, false, G5>(H, C, Cs, a, act, r0, i, xm, ls);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 1, LL>(acc, a, act, r0, xm, opar, xm, one, ls, H, ll);
+            lane_nbr<SP, RPT, 1, true, G5>(H, C, Cs, a, act, r0, i, yp, ls);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 1, LL>(acc, a, act, r0, yp, par, i, one, ls, H, ll);
+            lane_nbr<SP, RPT, 1, false, G5>(H, C, Cs, a, act, r0, i, ym, ls);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 1, LL>(acc, a, act, r0, ym, opar, ym, one, ls, H, ll);
+        } else {
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 0, LL>(acc, a, act, r0, xp, par, i, one, ls, nullptr, ll);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 0, LL>(acc, a, act, r0, xm, opar, xm, one, ls, nullptr, ll);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 0, LL>(acc, a, act, r0, yp, par, i, one, ls, nullptr, ll);
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 0, LL>(acc, a, act, r0, ym, opar, ym, one, ls, nullptr, ll);
+        }
+        // backward t-hop from the half kept since the last step (its registers are free after it)
+        const R sgn_tb = (NE == 6 && t == 0) ? -one : one;
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false, 1, LL, 0>(acc, a, act, r0, tm, opar, tm, sgn_tb, ls, pb, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true, 0, LL, 0>(acc, a, act, r0, zp, par, i, one, ls, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false, 0, LL, 1>(acc, a, act, r0, zm, opar, zm, one, ls, nullptr, ll);
+        {
+            // the input at (t + 1, p): forward half now, backward half for the next step
+            Cx<R> H[RPT][2][3];
+            {
+                Cx<R> v[RPT][12];
+                R vs[RPT];
+                load_raw<SP, RPT>(v, vs, a, act, r0, tp, ls);
+#pragma unroll
+                for (int r = 0; r < RPT; r++) {
+                    proj_in<SP, 3, true, G5>(v[r], vs[r], H[r]);
+                    proj_in<SP, 3, false, G5>(v[r], vs[r], pb[r]);
+                }
+            }
+            const R sgn_tf = (NE == 6 && t == Lt - 1) ? -one : one;
+            hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true, 1, LL, 0>(acc, a, act, r0, tp, par, i, sgn_tf, ls, H, ll);
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; r++) {
+            if (RPT > 1 && !act[r]) continue;
+            Cx<R> yv[12], zv[12], wv[12];
+            hop_finish<SP, false, 0>(a, i, valid, r0 + r, acc[r], yv, zv, wv, red[r], ls);
+        }
+    }
+    if (!any) return;
+
+    const int nv = red_nvals(a.red);
+    if (nv == 0) return;
+    const int ntiles = (int)gridDim.x / bpt;
+    const int ps = a.pstride ? a.pstride : ntiles;
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+        if (!act[r]) continue;
+        double *dst = a.partials + (size_t)(r0 + r) * nv * ps + tid;
+        if (nv == 1) {
+            double v[1] = {red[r][0]};
+            if (wsplit) wave_reduce_to<1>(v, dst, ps);
+            else block_reduce_to<1>(v, dst, ps);
+        } else if (nv == 2) {
+            double v[2] = {red[r][0], red[r][1]};
+            if (wsplit) wave_reduce_to<2>(v, dst, ps);
+            else block_reduce_to<2>(v, dst, ps);
+        } else {
+            double v[3] = {red[r][0], red[r][1], red[r][2]};
+            if (wsplit) wave_reduce_to<3>(v, dst, ps);
+            else block_reduce_to<3>(v, dst, ps);
+        }
+    }
+}
+
+template <int SP, int GP, int NE, bool G5, bool LNT, bool SHX, bool LL>
+static hipError_t launch_hop_tm(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
+    const int ngroups = a.nrhs / c.rpt;
+    const dim3 grid(hop_nblocks(a, c) * (c.wsplit ? ngroups / (c.block / 64) : ngroups)), block(c.block);
+    switch (c.rpt) {
+        case 1:
+            hipLaunchKernelGGL((hop_kernel_tm<SP, GP, 1, NE, G5, LNT, SHX, LL>), grid, block, 0, s, a, c.xcd, c.tm,
+                               c.wsplit);
+            break;
+        case 2:
+            if constexpr (!SHX)
+                hipLaunchKernelGGL((hop_kernel_tm<SP, GP, 2, NE, G5, LNT, false, LL>), grid, block, 0, s, a, c.xcd,
+                                   c.tm, c.wsplit);
+            else return hipErrorInvalidValue;
+            break;
+        case 3:
+        case 4:
+            if constexpr (SP != P64 && !SHX && !LL) {
+                if (c.rpt == 3)
+                    hipLaunchKernelGGL((hop_kernel_tm<SP, GP, 3, NE, G5, LNT, false, false>), grid, block, 0, s, a,
+                                       c.xcd, c.tm, c.wsplit);
+                else
+                    hipLaunchKernelGGL((hop_kernel_tm<SP, GP, 4, NE, G5, LNT, false, false>), grid, block, 0, s, a,
+                                       c.xcd, c.tm, c.wsplit);
+            } else {
+                return hipErrorInvalidValue;
+            }
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // Lattices too small to fill the GPU: with one wave per 64 sites most of it idles, and a
 // wave's time is its chain of dependent gathers.  Here five waves share a tile of 64
 // sites (one right-hand side per block): wave 1 + mu does the two hops along mu and leaves
@@ -572,7 +792,7 @@ __global__ void __launch_bounds__(320) hop_kernel_ds(const HopArgs a, int xcd_re
                          ((part[0][e + 1][lane] + part[1][e + 1][lane]) + part[2][e + 1][lane]) + part[3][e + 1][lane]};
         }
     double red[3] = {0.0, 0.0, 0.0};
-    hop_finish<SP, CLV, 1>(a, i, valid, rhs, acc, yv, zv, wd, red);
+    hop_finish<SP, CLV, 1>(a, i, valid, rhs, acc, yv, zv, wd, red, stride);
     const int nv = red_nvals(a.red);
     if (nv == 0) return;
     const int ntiles = (int)gridDim.x / a.nrhs;
@@ -662,6 +882,18 @@ static hipError_t launch_hop_ll(const HopArgs &a, const LaunchCfg &c, hipStream_
 template <int SP, int GP, int NE, bool G5>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const bool lnt = a.nrhs == c.rpt;
+    if (c.tm) {
+        if (c.ldsl) {
+            if constexpr (GP == P64 && NE == 9) return hipErrorInvalidValue;
+            else return c.shx ? launch_hop_tm<SP, GP, NE, G5, false, true, true>(a, c, s)
+                              : launch_hop_tm<SP, GP, NE, G5, false, false, true>(a, c, s);
+        }
+        if (c.shx)
+            return lnt ? launch_hop_tm<SP, GP, NE, G5, true, true, false>(a, c, s)
+                       : launch_hop_tm<SP, GP, NE, G5, false, true, false>(a, c, s);
+        return lnt ? launch_hop_tm<SP, GP, NE, G5, true, false, false>(a, c, s)
+                   : launch_hop_tm<SP, GP, NE, G5, false, false, false>(a, c, s);
+    }
     if (c.ldsl) {
         if constexpr (GP == P64 && NE == 9) return hipErrorInvalidValue;  // 72 KB of links per tile
         else return c.shx ? launch_hop_ll<SP, GP, NE, G5, true>(a, c, s) : launch_hop_ll<SP, GP, NE, G5, false>(a, c, s);

@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) gauge_pack_kernel(void *dst, const double
             const double2 d = idx < ne ? src[idx] : make_double2(0.0, 0.0);
             x[k] = {(R)(sgn * d.x), (R)(sgn * d.y)};
         }
-        st_link_elem<P, R>(const_cast<char *>(lplane<P>(dst, (par * 4 + mu) * nl + e, g.stride)), off, x);
+        st_link_elem<P, R>(const_cast<gchar *>(lplane<P>(dst, (par * 4 + mu) * nl + e, g.stride)), off, x);
     }
 }
 

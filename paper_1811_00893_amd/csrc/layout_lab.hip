@@ -108,7 +108,7 @@ __device__ __forceinline__ void lab_dir(Cx<real_t<P>> (&acc)[4][3], const LabArg
     Cx<R> U[3][3];
     {
         Cx<R> ue[NLE * CPE];
-        const char *lb = static_cast<const char *>(a.U[lpar]);
+        const gchar *lb = gptr(static_cast<const char *>(a.U[lpar]));
 #pragma unroll
         for (int e = 0; e < NLE; e++) ld_elem<P, R>(&ue[e * CPE], lb + lab_off<LAY>(lslot, MU * NLE + e, 4 * NLE, pad), 0u);
 #pragma unroll
@@ -125,7 +125,7 @@ __device__ __forceinline__ void lab_dir(Cx<real_t<P>> (&acc)[4][3], const LabArg
     // the t-hops need one spin half of the neighbour (upper forward, lower backward)
     constexpr int half = MU == 3 ? (FWD ? 1 : 0) : -1;
     Cx<R> comp[12];
-    const char *sb = static_cast<const char *>(a.in);
+    const gchar *sb = gptr(static_cast<const char *>(a.in));
 #pragma unroll
     for (int e = 0; e < NEL; e++) {
         const bool need = half < 0 || (e * CPE >= 6 * half && e * CPE < 6 * half + 6);
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) lab_hop_kernel(const LabArgs a, int xcd) 
     for (int s = 0; s < 4; s++)
 #pragma unroll
         for (int k = 0; k < 3; k++) o[s * 3 + k] = cscale(acc[s][k], cH);
-    char *ob = static_cast<char *>(a.out);
+    gchar *ob = gptr_w(static_cast<char *>(a.out));
 #pragma unroll
     for (int e = 0; e < NEL; e++) st_elem<P, R>(ob + lab_off<LAY>(slot, e, NEL, g.pad), 0u, &o[e * CPE]);
 }
@@ -223,7 +223,7 @@ __global__ void lab_pack_spinor_kernel(void *dst, const double2 *canon, const La
     Cx<double> v[12];
     for (int k = 0; k < 12; k++) v[k] = {canon[(size_t)s * 12 + k].x, canon[(size_t)s * 12 + k].y};
     for (int e = 0; e < NEL; e++)
-        st_elem<P, double>(static_cast<char *>(dst) + lab_off<LAY>(slot, e, NEL, g.pad), 0u, &v[e * CPE]);
+        st_elem<P, double>(gptr_w(static_cast<char *>(dst)) + lab_off<LAY>(slot, e, NEL, g.pad), 0u, &v[e * CPE]);
 }
 
 template <int LAY, int P>
@@ -234,7 +234,7 @@ __global__ void lab_unpack_spinor_kernel(double2 *canon, const void *src, const 
     const int s = lab_global_site(g, lab_decode<LAY>(g, slot, par));
     Cx<double> v[12];
     for (int e = 0; e < NEL; e++)
-        ld_elem<P, double>(&v[e * CPE], static_cast<const char *>(src) + lab_off<LAY>(slot, e, NEL, g.pad), 0u);
+        ld_elem<P, double>(&v[e * CPE], gptr(static_cast<const char *>(src)) + lab_off<LAY>(slot, e, NEL, g.pad), 0u);
     for (int k = 0; k < 12; k++) canon[(size_t)s * 12 + k] = make_double2(v[k].re, v[k].im);
 }
 
@@ -256,7 +256,7 @@ __global__ void lab_pack_links_kernel(void *dst, const double2 *canonU, const La
             v[k] = {sg * u.x, sg * u.y};
         }
         for (int e = 0; e < nle; e++)
-            st_elem<P, double>(static_cast<char *>(dst) + lab_off<LAY>(slot, mu * nle + e, 4 * nle, g.pad), 0u,
+            st_elem<P, double>(gptr_w(static_cast<char *>(dst)) + lab_off<LAY>(slot, mu * nle + e, 4 * nle, g.pad), 0u,
                                &v[e * CPE]);
     }
 }

@@ -167,7 +167,7 @@ TuneTable &tune_table() {
         std::ifstream in(T->path);
         std::string line;
         // one JSON object per line: {"key": "...", "block": B, "rpt": R, "xcd": X, "zblk": Z, "lds_kb": K,
-        // "wsplit": W, "shx": S, "dsplit": D, "ldsl": K, "ms": T}
+        // "wsplit": W, "shx": S, "dsplit": D, "ldsl": K, "tm": M, "ms": T}
         while (std::getline(in, line)) {
             const size_t k0 = line.find("\"key\": \"");
             if (k0 == std::string::npos) continue;
@@ -177,8 +177,9 @@ TuneTable &tune_table() {
             wl::LaunchCfg c;
             if (std::sscanf(line.c_str() + k1,
                             "\", \"block\": %d, \"rpt\": %d, \"xcd\": %d, \"zblk\": %d, \"lds_kb\": %d, \"wsplit\": %d, "
-                            "\"shx\": %d, \"dsplit\": %d, \"ldsl\": %d",
-                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit, &c.shx, &c.dsplit, &c.ldsl) >= 5)
+                            "\"shx\": %d, \"dsplit\": %d, \"ldsl\": %d, \"tm\": %d",
+                            &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb, &c.wsplit, &c.shx, &c.dsplit, &c.ldsl,
+                            &c.tm) >= 5)
                 T->cfg[key] = c;
         }
         return T;
@@ -191,7 +192,8 @@ void TuneTable::save(const std::string &key, const wl::LaunchCfg &c, double ms) 
     std::ofstream out(path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << c.block << ", \"rpt\": " << c.rpt << ", \"xcd\": " << c.xcd
         << ", \"zblk\": " << c.zblk << ", \"lds_kb\": " << c.lds_kb << ", \"wsplit\": " << c.wsplit
-        << ", \"shx\": " << c.shx << ", \"dsplit\": " << c.dsplit << ", \"ldsl\": " << c.ldsl << ", \"ms\": " << ms
+        << ", \"shx\": " << c.shx << ", \"dsplit\": " << c.dsplit << ", \"ldsl\": " << c.ldsl << ", \"tm\": " << c.tm
+        << ", \"ms\": " << ms
         << "}\n";
 }
 
@@ -220,6 +222,7 @@ static LaunchCfg fit_cfg(const HopArgs &a, LaunchCfg c) {
         c.dsplit = 0;
         c.block = 256;
     }
+    if (c.tm && !hop_cfg_valid(a, c)) c.tm = 0;
     if (c.ldsl && !hop_cfg_valid(a, c)) c.ldsl = 0;
     if (a.clov_mode != CLV_NONE) {
         c.rpt = 1;
@@ -292,6 +295,25 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
                     c.ldsl = 1;
                     if (a.nrhs > 1 && hop_cfg_valid(a, c)) cands.push_back(c);
                 }
+    // t-marching over 2, 4 or 8 slices: direct links (one or all RHS groups per block) or, with
+    // the wave split, links staged in LDS per step
+    for (int tm : {2, 4, 8})
+        for (int wsplit : {0, 1})
+            for (int ldsl : {0, 1})
+                for (int shx : {0, 1})
+                    for (int block : {64, 128, 192, 256})
+                        for (int rpt : {1, 2, 3, 4}) {
+                            if (ldsl && !wsplit) continue;
+                            if (wsplit && a.nrhs == 1) continue;
+                            LaunchCfg c;
+                            c.block = block;
+                            c.rpt = rpt;
+                            c.wsplit = wsplit;
+                            c.ldsl = ldsl;
+                            c.shx = shx;
+                            c.tm = tm;
+                            if (hop_cfg_valid(a, c)) cands.push_back(c);
+                        }
     for (int xcd : {1, 0}) {  // the direction split (small lattices)
         LaunchCfg c;
         c.block = 320;
@@ -318,9 +340,9 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         WL_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
         if (std::getenv("WILSON_TUNE_VERBOSE"))
-            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d shx=%d ds=%d ll=%d: %.2f us\n",
+            std::fprintf(stderr, "[tune] %s block=%d rpt=%d xcd=%d zblk=%d lds=%d ws=%d shx=%d ds=%d ll=%d tm=%d: %.2f us\n",
                          hop_key(a).c_str(), c.block, c.rpt, c.xcd, c.zblk, c.lds_kb, c.wsplit, c.shx, c.dsplit, c.ldsl,
-                         per * 1e3);
+                         c.tm, per * 1e3);
         if (per < bms) {
             bms = per;
             best = c;
@@ -342,8 +364,8 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
         const char *fc = std::getenv("WILSON_HOP_CFG");
         if (fc) {
             LaunchCfg &c = ctx->forced_cfg;
-            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb,
-                                      &c.wsplit, &c.shx, &c.dsplit, &c.ldsl) >= 4;
+            ctx->forced = std::sscanf(fc, "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &c.block, &c.rpt, &c.xcd, &c.zblk, &c.lds_kb,
+                                      &c.wsplit, &c.shx, &c.dsplit, &c.ldsl, &c.tm) >= 4;
         }
     }
     LaunchCfg cfg;

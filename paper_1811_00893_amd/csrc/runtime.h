@@ -117,7 +117,7 @@ struct wilson_gauge {
 // Hop launch configurations chosen by the autotuner, shared by every context of the
 // process (a configuration is a property of the device and the launch shape).
 //   WILSON_TUNE=0                       no tuning: built-in default configuration
-//   WILSON_HOP_CFG="block,rpt,xcd,zblk[,lds_kb[,wsplit[,shx[,dsplit[,ldsl]]]]]"   pin every hop launch of a context
+//   WILSON_HOP_CFG="block,rpt,xcd,zblk[,lds_kb[,wsplit[,shx[,dsplit[,ldsl[,tm]]]]]]"   pin every hop launch of a context
 //                                       created after it is set (tests)
 //   WILSON_TUNE_CACHE=path              JSON lines read at start, new entries appended
 //   WILSON_TUNE_VERBOSE=1               print every timed candidate

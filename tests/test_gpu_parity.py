@@ -220,7 +220,8 @@ def test_batched_point_sources(L, ctx):
 
 
 @pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1", "320,1,1,0,0,0,0,1",
-                                 "256,1,1,4,0,1,1,0,1", "128,2,1,0,0,1,0,0,1"])
+                                 "256,1,1,4,0,1,1,0,1", "128,2,1,0,0,1,0,0,1",
+                                 "256,1,1,0,0,1,1,0,1,2", "128,3,1,0,0,1,0,0,0,4", "64,2,1,0,0,0,0,0,0,1"])
 def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
     """The batched solve with the hop's RHS groups split over the waves of a block (each
     wave writes its own partial sums of the fused reductions; also with the tile's links
@@ -258,7 +259,8 @@ def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
             L.wilson_context_destroy(c)
 
 
-@pytest.mark.parametrize("cfg", ["256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1"])
+@pytest.mark.parametrize("cfg", ["256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1",
+                                 "256,1,1,0,0,0,1,0,0,2", "64,1,1,0,0,0,0,0,0,4"])
 def test_solves_with_lane_exchange(L, cfg, monkeypatch):
     """Solves whose hops take x/y neighbours from other lanes, or split the eight
     directions over the waves of a block: BiCGStab and CGNR (gamma5 on the hop input and
@@ -345,16 +347,22 @@ def test_full_size_sampled_dslash(L, ctx):
                                  "128,1,1,0,0,1", "256,1,1,2,0,1", "128,2,0,0,0,1", "256,1,1,0,40,1",
                                  "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,1,1,0,0,1,1", "256,1,1,2,0,0,1",
                                  "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1", "256,1,1,0,0,1,1,0,1",
-                                 "128,2,1,2,0,1,0,0,1"])
+                                 "128,2,1,2,0,1,0,0,1",
+                                 # t-marching over 5 or 1 slices of one t-parity: plain, two RHS per
+                                 # lane, lane exchange, wave split with links in LDS, wave split
+                                 # in plain block order, four RHS per lane (FP64: two)
+                                 "64,1,1,0,0,0,0,0,0,5", "128,2,1,0,0,0,0,0,0,1", "64,1,1,0,0,0,1,0,0,5",
+                                 "256,1,1,0,0,1,1,0,1,5", "128,1,0,0,0,1,0,0,0,1", "64,4,1,0,0,0,0,0,0,5"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
     XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
     waves of a block (with or without the tile's links staged in LDS), x/y neighbours
-    exchanged between lanes, directions split over the waves of a block) gives the
-    oracle's result;
+    exchanged between lanes, directions split over the waves of a block, blocks marching
+    through t-slices) gives the oracle's result;
     the lattice has a ragged last block for every block size, rows of 3 sites (x wraps
-    inside most wavefronts) and, with plane blocking, wavefronts whose sites are not
-    contiguous."""
+    inside most wavefronts), with plane blocking wavefronts whose sites are not
+    contiguous, and (t-marching) slices of 96 positions, so the last segment of each
+    slice is ragged."""
     monkeypatch.setenv("WILSON_HOP_CFG", cfg)
     dims = (6, 4, 8, 10)  # Vh = 960: not a multiple of 64, 128 or 256
     U, _ = setup_case(dims, 9)
