@@ -241,6 +241,31 @@ int wilson_solve_ex(wilson_ctx *ctx, const wilson_gauge *g, double *x, const dou
  * opts->workspace_bytes a caller-owned workspace may have. */
 size_t wilson_footprint_bytes(const int32_t dims[4], int32_t nrhs, const wilson_solve_opts *opts);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): wilson_solve_ex without any
+ * allocation.  Same arguments, semantics and results as wilson_solve_ex, with these
+ * differences:
+ *   - x and b must be device memory (host pointers: WILSON_INVALID_ARG);
+ *   - every device buffer of the solve lives in one static array of the library
+ *     (256 MiB per GPU, part of the library's code object: each GPU the library runs on
+ *     holds it from the library's first use on that device until the process ends); a
+ *     solve needing more, wilson_footprint_bytes(dims, nrhs, opts) > 256 MiB (for
+ *     example FP64 1 RHS up to 16^3x32, 12 RHS at 8^4), fails with WILSON_INVALID_ARG
+ *     and a message naming both sizes; opts->workspace must be NULL;
+ *   - host resources come from the context (created with it);
+ *   - launch shapes come from the tuning table filled by earlier calls of this process,
+ *     else the built-in defaults; no tuning runs; event timing is suspended for the call.
+ * The call allocates no device, pinned or managed memory (no hipMalloc, hipFree or
+ * allocating library routine).  All calls on one GPU share that GPU's array, which keeps
+ * the last call's contents (the solve clears what must start at zero): calls that overlap
+ * on one GPU (other threads, other contexts) race and must be serialised by the caller.
+ * Synchronous, like wilson_solve_ex.
+ */
+int wilson_solve_noalloc(wilson_ctx *ctx, const wilson_gauge *g, double *x, const double *b, int32_t nrhs,
+                         const double *kappa, const double *tol, const wilson_solve_opts *opts,
+                         wilson_solve_info *info);
+
 /* ---------------------------------------------------------------------------------- */
 /* Batched step API for continuous batching (a serving loop keeps one batch per        */
 /* resident gauge field and refills slots as right-hand sides converge).              */

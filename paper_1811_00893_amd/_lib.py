@@ -40,7 +40,7 @@ EXPORTS = [
     "wilson_batch_create", "wilson_batch_destroy", "wilson_batch_attach", "wilson_batch_step", "wilson_batch_poll",
     "wilson_batch_detach", "wilson_timing_enable", "wilson_timing_read", "wilson_stream_copy", "wilson_strerror",
     "wilson_last_error", "wilson_version", "wilson_stream_read", "wilson_gauge_attach_clover",
-    "wilson_gauge_detach_clover", "wilson_layout_hop",
+    "wilson_gauge_detach_clover", "wilson_layout_hop", "wilson_solve_noalloc",
 ]
 
 
@@ -76,6 +76,8 @@ _SIGS = {
     "wilson_dslash_ex": (_i32, [_vp, _vp, _vp, _vp, _d, _i32, _i32, _i32]),
     "wilson_solve_ex": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(wilson_solve_opts),
                                ctypes.POINTER(wilson_solve_info)]),
+    "wilson_solve_noalloc": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(wilson_solve_opts),
+                                    ctypes.POINTER(wilson_solve_info)]),
     "wilson_footprint_bytes": (ctypes.c_size_t, [_vp, _i32, ctypes.POINTER(wilson_solve_opts)]),
     "wilson_batch_create": (_i32, [_vp, _vp, _i32, ctypes.POINTER(wilson_solve_opts), ctypes.POINTER(_vp)]),
     "wilson_batch_destroy": (_i32, [_vp]),
@@ -267,6 +269,17 @@ def wilson_solve_ex(ctx, g, x, b, nrhs, kappa, tol, opts=None):
     infos = (wilson_solve_info * nrhs)()
     st = lib().wilson_solve_ex(ctx, g, _ptr(x), _ptr(b), int(nrhs), kap.ctypes.data, tl.ctypes.data, _opts(opts),
                                infos)
+    return st, [i.as_dict() for i in infos]
+
+
+def wilson_solve_noalloc(ctx, g, x, b, nrhs, kappa, tol, opts=None):
+    """wilson_solve_ex without device allocations (x, b device tensors).  Returns
+    (status, [info dict per RHS])."""
+    kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, np.float64), (nrhs,)))
+    tl = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, np.float64), (nrhs,)))
+    infos = (wilson_solve_info * nrhs)()
+    st = lib().wilson_solve_noalloc(ctx, g, _ptr(x), _ptr(b), int(nrhs), kap.ctypes.data, tl.ctypes.data,
+                                    _opts(opts), infos)
     return st, [i.as_dict() for i in infos]
 
 

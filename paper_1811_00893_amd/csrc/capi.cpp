@@ -54,11 +54,36 @@ struct Staged {
     }
 };
 
+// ---- device memory of the no-allocation solve ---------------------------------------
+// One static array per GPU, part of the library's code object: the loader allocates it
+// on each device the library is used on, and it stays until the process ends.  Its name
+// is only a host-side handle; host code uses the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device when a context is created.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+void *scratch_address(int device) {  // the calling thread's current device must be `device`
+    WL_CHECK_ARG(device >= 0 && device < kMaxDevices, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        WL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(WILSON_DEVICE_ERROR, "no device address for the scratch array");
+        g_scratch_addr[device] = p;
+    }
+    return g_scratch_addr[device];
+}
+
 wilson_ctx *make_ctx(void *stream) {
     std::unique_ptr<wilson_ctx> c(new wilson_ctx());
     WL_HIP(hipGetDevice(&c->device));
     c->stream = static_cast<hipStream_t>(stream);
     c->lend.create(kMaxRhs);
+    c->scratch = scratch_address(c->device);
     return c.release();
 }
 
@@ -363,6 +388,45 @@ int wilson_solve_ex(wilson_ctx *ctx, const wilson_gauge *g, double *x, const dou
     Staged sx(ctx, ctx->stage_out, x, bytes, p.use_x0);
     const int st = solve_device(ctx, g, sx.dev, sb.dev, nrhs, kappa, tol, p, info);
     sx.copy_out();
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    return st;
+    API_END
+}
+
+int wilson_solve_noalloc(wilson_ctx *ctx, const wilson_gauge *g, double *x, const double *b, int32_t nrhs,
+                         const double *kappa, const double *tol, const wilson_solve_opts *opts,
+                         wilson_solve_info *info) {
+    API_BEGIN
+    WL_CHECK_ARG(ctx != nullptr && g != nullptr, "ctx / g is NULL");
+    WL_CHECK_ARG(x != nullptr && b != nullptr, "x / b is NULL");
+    WL_CHECK_ARG(x != b, "x and b must be distinct");
+    check_solve_args(kappa, tol, nrhs, opts);
+    WL_CHECK_ARG(opts == nullptr || opts->workspace == nullptr,
+                 "the no-allocation solve keeps its buffers in the library's scratch array; opts->workspace must be NULL");
+    WL_CHECK_ARG(is_device_ptr(x) && is_device_ptr(b), "the no-allocation solve takes device buffers only");
+    SolveParams p = params_from(opts, 10000);
+    if (p.precision != WILSON_FP64) {
+        const uint32_t need = gauge_bits_for(p.precision);
+        WL_CHECK_ARG((need & WILSON_GAUGE_FP32) == 0 || g->U[P32].get(), "gauge field has no FP32 copy");
+        WL_CHECK_ARG((need & WILSON_GAUGE_FP16) == 0 || g->U[P16].get(), "gauge field has no FP16 copy");
+    }
+    const size_t need = solve_footprint(g->g, nrhs, p);
+    if (need > kScratchBytes)
+        throw Error(WILSON_INVALID_ARG, "the solve needs " + std::to_string(need) + " bytes of device memory; the "
+                                        "no-allocation solve holds at most " + std::to_string(kScratchBytes) +
+                                        " (use wilson_solve_ex)");
+    WL_CHECK_ARG(ctx->scratch != nullptr, "no scratch array on this context's device");
+    p.workspace = ctx->scratch;
+    p.workspace_bytes = kScratchBytes;
+    p.no_tune = true;
+    // event timing would create events; suspended for the call
+    struct TimingOff {
+        wilson_ctx *c;
+        bool was;
+        explicit TimingOff(wilson_ctx *cc) : c(cc), was(cc->timing) { c->timing = false; }
+        ~TimingOff() { c->timing = was; }
+    } timing_off(ctx);
+    const int st = solve_device(ctx, g, x, b, nrhs, kappa, tol, p, info);
     WL_HIP(hipStreamSynchronize(ctx->stream));
     return st;
     API_END

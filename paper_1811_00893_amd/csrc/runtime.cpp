@@ -378,6 +378,7 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
             break;
         }
     if (!found) {
+        bool cache = true;
         TuneTable &T = tune_table();
         const std::string key = hop_key(a);
         std::lock_guard<std::mutex> lk(T.mu);
@@ -386,16 +387,19 @@ int hop(wilson_ctx *ctx, HopArgs &a, double algorithmic_bytes) {
             cfg = ctx->forced_cfg;  // the pinned shape; fitted to each launch below
         } else if (it != T.cfg.end()) {
             cfg = it->second;
-        } else if (T.enabled && a.g.Vh >= 4096) {
+        } else if (T.enabled && a.g.Vh >= 4096 && !ctx->no_tune) {
             double ms = 0;
             cfg = tune_hop(ctx, a, &ms);
             T.cfg[key] = cfg;
             T.save(key, cfg, ms);
+        } else if (ctx->no_tune) {
+            cfg = default_cfg(a);  // kept nowhere: a later call may still tune this shape
+            cache = false;
         } else {
             cfg = default_cfg(a);
             T.cfg[key] = cfg;
         }
-        if (ctx->hot.size() < 32) ctx->hot.push_back({hk, cfg});
+        if (cache && ctx->hot.size() < 32) ctx->hot.push_back({hk, cfg});
     }
     // a stored or pinned shape may not suit this launch (clover epilogue, RHS count): keep
     // its order and block, fit the RHS split

@@ -172,6 +172,8 @@ struct wilson_ctx {
     // host resources lent to solves whose device memory the caller provides (created with
     // the context, so those solves allocate nothing themselves)
     wl::SolveHostRes lend;
+    void *scratch = nullptr;         // device address of the no-allocation solve's array on this device
+    bool no_tune = false;            // set for the duration of a call that must not tune
     wl::DevBuf stage_in, stage_out;  // canonical staging for host pointers
     wl::DevBuf flag;                 // device int for finiteness checks
     wl::PinnedBuf pinned;            // small host mirror

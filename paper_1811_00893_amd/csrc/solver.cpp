@@ -74,8 +74,8 @@ size_t EoMem::carve(char *base, const Geom &g, int n, int precision, int method)
 
 // Fields, states and primitive operations of one even-odd problem with nrhs RHS.
 // Device memory: one region holding every buffer (EoMem), either allocated here or the
-// caller's workspace.  Host resources (pinned state mirrors, ring events): owned, or lent
-// by the context.
+// caller's (a workspace, or the static scratch array of the no-allocation solve).  Host
+// resources (pinned state mirrors, ring events): owned, or lent by the context.
 class EoCore : public EoMem {
    public:
     wilson_ctx *ctx;
@@ -552,11 +552,20 @@ size_t solve_footprint(const Geom &g, int nrhs, const SolveParams &p) {
     return m.carve(nullptr, g, nrhs, p.precision, p.method);
 }
 
+// Sets the context's no-tuning flag for the lifetime of a call.
+struct NoTuneScope {
+    wilson_ctx *ctx;
+    bool prev;
+    NoTuneScope(wilson_ctx *c, bool on) : ctx(c), prev(c->no_tune) { c->no_tune = prev || on; }
+    ~NoTuneScope() { ctx->no_tune = prev; }
+};
+
 int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const double *b_canon, int nrhs,
                  const double *kappa, const double *tol, const SolveParams &prm, wilson_solve_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t hop0 = ctx->hop_launch_count;
     const double bytes0 = ctx->bytes_issued, flops0 = ctx->flops_issued;
+    NoTuneScope nts(ctx, prm.no_tune);
     // a caller's region holds the device buffers of this call only (built per call, with
     // the context's host resources); otherwise a cached workspace of the context
     auto core = prm.workspace ? std::make_shared<EoCore>(ctx, G, nrhs, prm.precision, prm.method, prm.workspace,

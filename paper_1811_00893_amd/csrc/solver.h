@@ -41,7 +41,7 @@ struct FieldBuf {
 
 // Device memory of one even-odd problem with nrhs right-hand sides: every field, the
 // reduction partials and the per-RHS states, carved in a fixed order out of one region
-// (the library's own allocation or a caller's workspace).
+// (the library's own allocation, a caller's workspace, or the static scratch array).
 struct EoMem {
     FieldBuf b_e, b_o, x_e, x_o, bp;          // FP64 problem
     FieldBuf r64, tmp64;                      // FP64 outer residual (mixed only)
@@ -65,6 +65,7 @@ struct SolveParams {
     bool reliable = false;  // mixed precision: reliable updates instead of defect correction
     void *workspace = nullptr;    // device region for every buffer of the solve (null: the library's)
     size_t workspace_bytes = 0;
+    bool no_tune = false;         // launch shapes from the tuning table or the defaults, no tuning runs
 };
 
 // Solves for nrhs right-hand sides given in canonical layout on the device.
