@@ -5,10 +5,14 @@ Default workload (one "step" = one whole solve): plain FP64 even-odd BiCGStab on
 relative residual 1e-10 (checked in FP64 after the iteration).  Sources and links are
 resident in HBM before the timed region starts.
 
-Printed: one JSON line with solves/s (value), p50/p99 latency, the achieved bandwidth of
-the dominant kernel (the parity hop, measured with HIP events on the library's stream
-over the timed region) against the MI355X HBM peak, a Dslash-only figure (parity hop
-alone), and the CPU oracle timed on a bounded sample of the same workload.
+Printed: one JSON line with solves/s (value), p50/p99 latency from a separate pass of 100
+solves, the achieved bandwidth of the dominant kernel (the parity hop, timed with HIP events
+on the library's stream) against the MI355X HBM peak on the algorithmic byte count, the
+bytes two-row links must move and the measured counter traffic, a Dslash-only figure (parity
+hop alone), the CPU oracle timed on the same workload (a full FP64 solve), and under
+"configs" the headline figures of the other configurations: 8^4 FP64, the three
+mixed-precision variants at 48^3x96 and the 12 point sources at 24^3x48 (each with its hop's
+roofline fractions and the gain over the plain FP64 solver; --no-extras leaves them out).
 
 Other workloads (not the headline line): --workload small8 | mixed48 | mixed48_fp16 | mixed48_fp16h |
 mixed48_reliable | mixed48_fp16_reliable | batched24 | batched24_fp16 | block24 | block24_k135 |
@@ -47,6 +51,11 @@ def parse():
     p.add_argument("--max-heavy", type=int, default=2,
                    help="serving: heavy batches (an iteration >= 0.5 ms) advancing at once, oldest first (0: no limit)")
     p.add_argument("--hbm-budget", type=float, default=200e9, help="serving: device bytes for fields + batches")
+    p.add_argument("--latency-samples", type=int, default=100, help="solves of the latency pass (p50/p99)")
+    p.add_argument("--extra-latency-samples", type=int, default=30,
+                   help="latency pass of the other configurations of the default run (8^4 takes 100)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="default run: leave out the other configurations (8^4, 48^3x96 mixed x 3, 24^3x48 batched)")
     return p.parse_args()
 
 
@@ -399,14 +408,30 @@ def run_layouts(args):
     }
 
 
-def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check=None, block=False):
-    """The FP64 oracle timed on the host: an even-odd BiCGStab solve (run for 1 and 1+k
-    iterations, whose difference isolates the cost of an iteration, scaled to the number
-    of iterations the GPU solve took), and the operator units (parity hop, full D) with
-    all threads and the parity hop on one thread.  With `check` (GPU results copied to the
-    host: a solution x of right-hand side xb, and an operator output dout of input din with
-    its parity dpar), the oracle's FP64 operator also grades them: |xb - D x| / |xb| and
-    |dout - oracle| / |oracle| (outside the timed region)."""
+def host_info(nthr):
+    host = {"cpu_model": None, "logical_cpus": os.cpu_count(), "cpus_in_affinity": len(os.sched_getaffinity(0)),
+            "omp_threads_used": nthr, "omp_proc_bind": os.environ.get("OMP_PROC_BIND"),
+            "omp_places": os.environ.get("OMP_PLACES")}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    host["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return host
+
+
+def cpu_baseline(args, U, b, kappa, tol, dims, nrhs, precision, it_gpu, F=None, check=None, block=False):
+    """The FP64 oracle timed on the host's cores.  Plain FP64 Wilson workloads with one
+    right-hand side up to 32^3x64: a full even-odd BiCGStab solve of the same problem to the
+    same tolerance (value = 1 / its time), on one core too when it takes under half a
+    second; others: setup + per-iteration cost x the GPU's iteration count (the difference
+    of a 1- and a (1+k)-iteration run, about `--cpu-seconds` of work).  Also the operator
+    units (parity hop with all threads and with one, full D) and the host triad.  With `check` (GPU results copied to the host: a solution x of
+    right-hand side xb, and an operator output dout of input din with its parity dpar), the
+    oracle's FP64 operator also grades them (outside the timed region)."""
     import numpy as np
 
     import oracle
@@ -415,23 +440,34 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
     bn = (b[0] if nrhs > 1 else b).cpu().numpy()
     Fn = None if F is None else F.cpu().numpy()
 
-    def solve(iters):
+    def solve(t, iters):
         if block:  # the oracle's block BiCGStab on all the right-hand sides
-            return oracle.solve_block(b.cpu().numpy(), Un, kappa, dims, 0.0, iters, F=Fn)
+            return oracle.solve_block(b.cpu().numpy(), Un, kappa, dims, t, iters, F=Fn)
         if Fn is None:
-            return oracle.solve(bn, Un, kappa, dims, 0.0, iters, "bicgstab_eo")
-        return oracle.solve_clov(bn, Un, Fn, kappa, dims, 0.0, iters, "bicgstab_eo")
+            return oracle.solve(bn, Un, kappa, dims, t, iters, "bicgstab_eo")
+        return oracle.solve_clov(bn, Un, Fn, kappa, dims, t, iters, "bicgstab_eo")
 
-    t1 = time.perf_counter()
-    solve(1)
-    one = time.perf_counter() - t1
-    k_it = max(2, min(40, int(args.cpu_seconds / max(one, 1e-3))))
-    t1 = time.perf_counter()
-    solve(1 + k_it)
-    more = time.perf_counter() - t1
-    per_iter = max(more - one, 1e-9) / k_it
-    setup = max(one - per_iter, 0.0)
+    full = None
+    nthr = oracle.num_threads()
     V = int(np.prod(dims))
+    one = more = 0.0
+    k_it = 0
+    per_iter = setup = None
+    if not block and Fn is None and nrhs == 1 and precision == 0 and V <= (1 << 21):
+        # the plain FP64 workloads up to 32^3x64: one full solve (about 10 s at 32^3x64)
+        t1 = time.perf_counter()
+        _, st, tres = solve(tol, 20000)
+        full = {"seconds": time.perf_counter() - t1, "iterations": st, "true_residual": tres}
+    else:
+        t1 = time.perf_counter()
+        solve(0.0, 1)
+        one = time.perf_counter() - t1
+        k_it = max(2, min(40, int(args.cpu_seconds / max(one, 1e-3))))
+        t1 = time.perf_counter()
+        solve(0.0, 1 + k_it)
+        more = time.perf_counter() - t1
+        per_iter = max(more - one, 1e-9) / k_it
+        setup = max(one - per_iter, 0.0)
 
     def best_of(fn, n=3):
         ts = []
@@ -446,10 +482,14 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
         d_s = best_of(lambda: oracle.apply_D(bn, Un, kappa, dims))
     else:
         d_s = best_of(lambda: oracle.apply_Dclov(bn, Un, Fn, kappa, dims))
-    nthr = oracle.num_threads()
     oracle.set_threads(1)
     try:
         hop1_s = best_of(lambda: oracle.dslash(bn, Un, kappa, dims, 0), n=1)
+        one_core_full = None
+        if full is not None and full["seconds"] < 0.5:  # small lattices: the whole solve on one core
+            t1 = time.perf_counter()
+            solve(tol, 20000)
+            one_core_full = time.perf_counter() - t1
     finally:
         oracle.set_threads(nthr)
     triad = oracle.triad_gbps()
@@ -468,160 +508,45 @@ def cpu_baseline(args, U, b, kappa, dims, nrhs, precision, it_gpu, F=None, check
             "operator": ("D_clov" if Fn is not None else ("parity hop" if dpar < 2 else "D")) +
                         f" in the workload's precision ({['fp64', 'fp32', 'fp16', 'fp16 spinors + fp32 links'][precision]})",
         }
-    host = {"cpu_model": None, "logical_cpus": os.cpu_count(), "cpus_in_affinity": len(os.sched_getaffinity(0)),
-            "omp_threads_used": nthr, "omp_proc_bind": os.environ.get("OMP_PROC_BIND"),
-            "omp_places": os.environ.get("OMP_PLACES")}
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    host["cpu_model"] = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
     what = ("the same right-hand side" if nrhs == 1 else
             f"all {nrhs} right-hand sides in the oracle's block BiCGStab" if block else
             f"right-hand side 0 of the {nrhs}, the batch costed as {nrhs} sequential solves")
     inner = "" if precision == 0 else " (the GPU's inner iterations in reduced precision; the oracle is FP64)"
+    if full is not None:
+        value = 1.0 / full["seconds"]
+        sample = (f"FP64 oracle even-odd BiCGStab on {list(dims)}, {what}, one full solve to tol {tol:g} "
+                  f"({full['iterations']} iterations, {full['seconds']:.1f} s)")
+    else:
+        value = (nrhs if block else 1.0) / (setup + per_iter * it_gpu)
+        sample = (f"FP64 oracle even-odd {'block ' if block else ''}BiCGStab"
+                  f"{' (clover matrix)' if Fn is not None else ''} on {list(dims)}, {what}, run for 1 and "
+                  f"{1 + k_it} iterations ({one + more:.1f} s of CPU work); solve time = setup + per-iteration "
+                  f"cost x the {it_gpu:.0f} iterations the GPU solve needed{inner}")
     return {
-        "value": (nrhs if block else 1.0) / (setup + per_iter * it_gpu),
+        "value": value,
         "unit": "solves/s",
         "cores": nthr,
         "kind": "oracle",
-        "sample": f"FP64 oracle even-odd {'block ' if block else ''}BiCGStab"
-                  f"{' (clover matrix)' if Fn is not None else ''} on {list(dims)}, "
-                  f"{what}, run for 1 and {1 + k_it} "
-                  f"iterations ({one + more:.1f} s of CPU work); solve time = setup + per-iteration cost x "
-                  f"the {it_gpu:.0f} iterations the GPU solve needed{inner}",
+        "sample": sample,
+        "full_solve": full,
         "seconds_per_iteration": per_iter,
         "setup_seconds": setup,
+        "one_core": {"solve_s": one_core_full, "parity_hop_s": hop1_s},
         "units": {
             "parity_hop_s": hop_s,
             "parity_hop_gbs_algorithmic": (V // 2) * counts.hop_bytes_per_site("fp64") / hop_s / 1e9,
-            "parity_hop_one_thread_s": hop1_s,
             "full_d_s": d_s,
             "full_d_gflops": (counts.FULL_D_FLOPS_PER_SITE if Fn is None else counts.CLOVER_FLOPS_PER_SITE) * V / d_s / 1e9,
             "host_triad_gbs": triad,
         },
         "gpu_results_graded_by_oracle": graded,
-        "host": host,
+        "host": host_info(nthr),
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this library has no multi-GPU path (see the design notes on "
-              "how the lattice would shard); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "serve":
-        print(json.dumps(run_serving(args)), flush=True)
-        return
-    if args.workload == "layouts":
-        print(json.dumps(run_layouts(args)), flush=True)
-        return
-    import numpy as np
+def probes(L, ctx, dev):
+    """HBM references: a plain streaming copy and a read of 2 GiB (GB/s)."""
     import torch
-
-    from paper_1811_00893_amd import _lib as L
-    from paper_1811_00893_amd import counts, inputs
-
-    dims, kappa, tol, precision, nrhs, desc = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    V = int(np.prod(dims))
-    Vh = V // 2
-    t_setup = time.perf_counter()
-    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=dev)
-    nsrc = args.steps + args.warmup
-    if nrhs == 1:
-        srcs = [inputs.gaussian_source(dims, seed=2002 + i, device=dev) for i in range(nsrc)]
-    else:
-        pts = inputs.point_sources(dims, device=dev)
-        srcs = [pts for _ in range(nsrc)]
-    x = torch.zeros_like(srcs[0])
-    ctx = L.wilson_context_create()
-    gbits = L.WILSON_GAUGE_FP32 | (L.WILSON_GAUGE_FP16 if precision == 2 else 0)
-    g = L.wilson_gauge_load(ctx, U, dims, gbits)
-    clover = args.workload in CLOVER
-    F = None
-    if clover:
-        F = inputs.clover_field(dims, c=0.05, seed=1005, device=dev)
-        L.check(L.wilson_gauge_attach_clover(ctx, g, F, dims), "attach clover")
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t_setup
-    opts = {"precision": precision, "maxiter": 20000, "mixed_update": 1 if args.workload in RELIABLE else 0,
-            "solver": L.WILSON_SOLVER_BLOCK_BICGSTAB_EO if args.workload in BLOCK else L.WILSON_SOLVER_BICGSTAB_EO,
-            "inner_tol": args.inner_tol}
-
-    # ---- Dslash only: plain parity hop on resident fields (FP64 for the FP64 workload);
-    # for the clover matrix the hops of D_clov on both parities (T x - kappa H x) ----
-    dprec = precision  # the workload's inner precision
-    dpar = 2 if clover else 0
-    psi = srcs[0]  # all right-hand sides of the workload in one launch
-    out = torch.zeros_like(psi)
-    for _ in range(3):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, dpar, dprec, nrhs), "dslash")
-    torch.cuda.synchronize()
-    L.wilson_timing_enable(ctx, True)
-    for _ in range(args.dslash_reps):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, dpar, dprec, nrhs), "dslash")
-    torch.cuda.synchronize()
-    d_ms, d_n, d_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
-    L.wilson_timing_enable(ctx, False)
-    d_us = 1e3 * d_ms / max(d_n, 1)
-    d_gbs = d_bytes / (d_ms * 1e-3) / 1e9
-    sname = {0: "fp64", 1: "fp32", 2: "fp16", 3: "fp16"}[dprec]
-    lname = {0: "fp64", 1: "fp32", 2: "fp16", 3: "fp32"}[dprec]
-    dslash = {
-        "precision": sname,
-        "nrhs": nrhs,
-        "us_per_launch": d_us,
-        "launches": d_n,
-        "algorithmic_bytes_per_launch": d_bytes / max(d_n, 1),
-        "bytes_per_site": d_bytes / max(d_n, 1) / Vh,
-        "gbs": d_gbs,
-        "frac_hbm_peak": d_gbs / counts.MI355X_HBM_GBS,
-        "gflops": (counts.CLOVER_FLOPS_PER_SITE if clover else counts.HOP_FLOPS_PER_SITE) * Vh * nrhs
-                  / (d_us * 1e-6) / 1e9,
-        "working_set_mb": d_bytes / max(d_n, 1) / 1e6,
-    }
-    if clover:  # both hops of one D_clov application, with the paper's ideal byte count
-        per_app = 1e-6 * d_us * 2
-        dslash["d_clov"] = {
-            "us_per_application": 2 * d_us,
-            "gflops_1944": counts.CLOVER_FLOPS_PER_SITE * V * nrhs / per_app / 1e9,
-            "gbs_ideal_count": counts.clover_full_bytes_per_site(lname if lname != "fp16" else "fp32") * V / per_app / 1e9,
-        }
-
-    # ---- full D = 1 - kappa H on both parities (two hops, identity term fused); left out
-    # of --dslash-only runs, whose hop launches are then all plain parity hops ----
-    full_d = None
-    for _ in range(0 if (args.dslash_only or clover) else 2):
-        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
-    torch.cuda.synchronize()
-    if not args.dslash_only and not clover:
-        L.wilson_timing_enable(ctx, True)
-        reps_d = max(args.dslash_reps // 2, 1)
-        for _ in range(reps_d):
-            L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
-        torch.cuda.synchronize()
-        f_ms, f_n, f_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
-        L.wilson_timing_enable(ctx, False)
-        f_us = 1e3 * f_ms / reps_d
-        # the paper's count for D: each link, input and output read or written once per site
-        ideal_site = 4 * counts.link_bytes(lname) + nrhs * 2 * counts.spinor_site_bytes(sname)
-        full_d = {
-            "us_per_application": f_us,
-            "hop_launches_per_application": f_n / reps_d,
-            "gflops": counts.FULL_D_FLOPS_PER_SITE * V * nrhs / (f_us * 1e-6) / 1e9,
-            "ideal_bytes_per_site": ideal_site,
-            "gbs_ideal_count": ideal_site * V / (f_us * 1e-6) / 1e9,
-            "gbs_launch_count": f_bytes / (f_ms * 1e-3) / 1e9,
-        }
-    dslash["full_d"] = full_d
-    del out
-
-    # ---- HBM reference: a plain streaming copy of 2 GiB (not the workload) ----
     nb = 1 << 31
     src_buf = torch.empty(nb, dtype=torch.uint8, device=dev)
     dst_buf = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -642,26 +567,160 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     read_gbs = 10 * nb / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src_buf, dst_buf
-    dslash["frac_of_copy_bw"] = d_gbs / copy_gbs
-    if args.dslash_only:
-        print(json.dumps({"dslash": dslash, "hbm_copy_gbs": copy_gbs, "hbm_read_gbs": read_gbs}), flush=True)
-        return
+    return copy_gbs, read_gbs
 
-    # ---- solves ----
+
+def measure(args, name, steps, warmup, lat_samples, dslash_reps, with_cpu, full_d=True, host_lat=0,
+            compare=True):
+    """One workload: Dslash-only timing of the parity hop (the dominant kernel) with its
+    roofline fractions, `steps` timed solves after `warmup` (the timed region: sources and
+    links resident in HBM), a separate latency pass of `lat_samples` solves (p50 / p99 of
+    the call; the solution in HBM when it returns), optionally `host_lat` solves whose
+    solution is also copied to pinned host memory (latency to x on the host), the hop and
+    vector-kernel figures of solves run with event timing, the comparisons (sequential
+    single-RHS solves, the plain FP64 solver on the same problem, the lockstep solver for
+    block workloads) and the CPU oracle."""
+    import numpy as np
+    import torch
+
+    from paper_1811_00893_amd import _lib as L
+    from paper_1811_00893_amd import counts, inputs
+
+    dims, kappa, tol, precision, nrhs, desc = WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    V = int(np.prod(dims))
+    Vh = V // 2
+    t_setup = time.perf_counter()
+    U = inputs.gauge_field(dims, eps=0.3, seed=1002, device=dev)
+    nsrc = max(steps + warmup, 2)
+    if nrhs == 1:
+        srcs = [inputs.gaussian_source(dims, seed=2002 + i, device=dev) for i in range(nsrc)]
+    else:
+        pts = inputs.point_sources(dims, device=dev)
+        srcs = [pts for _ in range(nsrc)]
+    x = torch.zeros_like(srcs[0])
+    ctx = L.wilson_context_create()
+    gbits = L.WILSON_GAUGE_FP32 | (L.WILSON_GAUGE_FP16 if precision == 2 else 0)
+    g = L.wilson_gauge_load(ctx, U, dims, gbits)
+    clover = name in CLOVER
+    F = None
+    if clover:
+        F = inputs.clover_field(dims, c=0.05, seed=1005, device=dev)
+        L.check(L.wilson_gauge_attach_clover(ctx, g, F, dims), "attach clover")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    opts = {"precision": precision, "maxiter": 20000, "mixed_update": 1 if name in RELIABLE else 0,
+            "solver": L.WILSON_SOLVER_BLOCK_BICGSTAB_EO if name in BLOCK else L.WILSON_SOLVER_BICGSTAB_EO,
+            "inner_tol": args.inner_tol}
+
+    # ---- Dslash only: plain parity hop on resident fields (in the workload's inner
+    # precision); for the clover matrix the hops of D_clov on both parities ----
+    dprec = precision
+    dpar = 2 if clover else 0
+    psi = srcs[0]  # all right-hand sides of the workload in one launch
+    out = torch.zeros_like(psi)
+    for _ in range(3):
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, dpar, dprec, nrhs), "dslash")
+    torch.cuda.synchronize()
+    L.wilson_timing_enable(ctx, True)
+    for _ in range(dslash_reps):
+        L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, dpar, dprec, nrhs), "dslash")
+    torch.cuda.synchronize()
+    d_ms, d_n, d_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
+    L.wilson_timing_enable(ctx, False)
+    d_us = 1e3 * d_ms / max(d_n, 1)
+    d_gbs = d_bytes / (d_ms * 1e-3) / 1e9
+    sname = {0: "fp64", 1: "fp32", 2: "fp16", 3: "fp16"}[dprec]
+    lname = {0: "fp64", 1: "fp32", 2: "fp16", 3: "fp32"}[dprec]
+    per_launch = d_bytes / max(d_n, 1)
+    # bytes the kernel must move with its link storage: SU(3) links keep 12 of 18 reals
+    floor_launch = per_launch - (2 if clover else 1) * Vh * 8 * 6 * counts.REAL_BYTES[lname]
+    dslash = {
+        "precision": sname,
+        "link_precision": lname,
+        "nrhs": nrhs,
+        "us_per_launch": d_us,
+        "launches": d_n,
+        "algorithmic_bytes_per_launch": per_launch,
+        "floor_bytes_per_launch": floor_launch,
+        "bytes_per_site": per_launch / Vh,
+        "gbs": d_gbs,
+        "frac_hbm_peak": d_gbs / counts.MI355X_HBM_GBS,
+        "frac_floor": floor_launch / (d_us * 1e-6) / 1e9 / counts.MI355X_HBM_GBS,
+        "gflops": (counts.CLOVER_FLOPS_PER_SITE if clover else counts.HOP_FLOPS_PER_SITE) * Vh * nrhs
+                  / (d_us * 1e-6) / 1e9,
+        "working_set_mb": per_launch / 1e6,
+    }
+    if clover:  # both hops of one D_clov application, with the paper's ideal byte count
+        per_app = 1e-6 * d_us * 2
+        dslash["d_clov"] = {
+            "us_per_application": 2 * d_us,
+            "gflops_1944": counts.CLOVER_FLOPS_PER_SITE * V * nrhs / per_app / 1e9,
+            "gbs_ideal_count": counts.clover_full_bytes_per_site(lname if lname != "fp16" else "fp32") * V / per_app / 1e9,
+        }
+    fd = None
+    if full_d and not args.dslash_only and not clover:
+        for _ in range(2):
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
+        torch.cuda.synchronize()
+        L.wilson_timing_enable(ctx, True)
+        reps_d = max(dslash_reps // 2, 1)
+        for _ in range(reps_d):
+            L.check(L.wilson_dslash_ex(ctx, g, out, psi, kappa, 2, dprec, nrhs), "full D")
+        torch.cuda.synchronize()
+        f_ms, f_n, f_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
+        L.wilson_timing_enable(ctx, False)
+        f_us = 1e3 * f_ms / reps_d
+        # the paper's count for D: each link, input and output read or written once per site
+        ideal_site = 4 * counts.link_bytes(lname) + nrhs * 2 * counts.spinor_site_bytes(sname)
+        fd = {
+            "us_per_application": f_us,
+            "hop_launches_per_application": f_n / reps_d,
+            "gflops": counts.FULL_D_FLOPS_PER_SITE * V * nrhs / (f_us * 1e-6) / 1e9,
+            "ideal_bytes_per_site": ideal_site,
+            "gbs_ideal_count": ideal_site * V / (f_us * 1e-6) / 1e9,
+            "gbs_launch_count": f_bytes / (f_ms * 1e-3) / 1e9,
+        }
+    dslash["full_d"] = fd
+    del out
+    traffic = committed_traffic(name, dslash)
+    roofline = {
+        "bound": "hbm",
+        "kernel": (f"parity hop of D_clov (T x - kappa H x), {sname} spinors, {list(dims)}" if clover else
+                   f"parity hop (Dslash D_eo = -kappa H_eo), {sname} spinors, {lname} links, {nrhs} RHS, "
+                   f"{list(dims)}"),
+        "achieved": d_gbs,
+        "peak": counts.MI355X_HBM_GBS,
+        "unit": "GB/s",
+        "frac": d_gbs / counts.MI355X_HBM_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": per_launch,
+        "us_per_launch": d_us,
+        # the same time against the bytes the kernel must move with two-row (12-real) links,
+        # and against the HBM bytes the counters measured (when the summary is current)
+        "floor_bytes_per_launch": floor_launch,
+        "frac_floor": dslash["frac_floor"],
+        "frac_counter": (traffic / (d_us * 1e-6) / 1e9 / counts.MI355X_HBM_GBS) if traffic else None,
+        "frac_basis": "frac counts each link as 18 reals (Table 1's convention, the >= 70 % target); frac_floor "
+                      "counts the 12 reals the two-row link storage reads; frac_counter uses the measured traffic",
+    }
+    if args.dslash_only:
+        L.wilson_gauge_free(ctx, g)
+        L.wilson_context_destroy(ctx)
+        return {"dslash": dslash, "roofline": roofline, "setup_s": setup_s}
+
+    # ---- solves: the timed region ----
     kap = [kappa] * nrhs
     tl = [tol] * nrhs
-    for i in range(args.warmup):
+    for i in range(warmup):
         x.zero_()
         st, info = L.wilson_solve_ex(ctx, g, x, srcs[i], nrhs, kap, tl, opts)
         L.check(st, "warmup solve")
     torch.cuda.synchronize()
-    lat, iters, res, cycles = [], [], [], []
+    iters, res, cycles = [], [], []
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        s0 = time.perf_counter()
-        st, info = L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, opts)
-        lat.append(time.perf_counter() - s0)
+    for i in range(steps):
+        st, info = L.wilson_solve_ex(ctx, g, x, srcs[warmup + i], nrhs, kap, tl, opts)
         if st != 0:
             raise RuntimeError(f"solve {i} returned {st}: {L.wilson_last_error()}")
         iters.append(max(d["iterations"] for d in info))
@@ -669,37 +728,35 @@ def main():
         res.append(max(d["true_residual"] for d in info))
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    # the last timed solution, kept for the oracle's grading (later solves reuse x)
     x_last = (x[0] if nrhs > 1 else x).cpu().numpy()
-    # per-kernel figures from a separate pass with event timing on (event records around
-    # every launch would slow the launch-bound small lattices in the timed region)
-    n_prof = min(args.steps, 3)
+    # ---- latency: a separate pass, every call timed on its own ----
+    lat = []
+    for i in range(lat_samples):
+        s0 = time.perf_counter()
+        st, _ = L.wilson_solve_ex(ctx, g, x, srcs[(warmup + i) % nsrc], nrhs, kap, tl, opts)
+        lat.append(time.perf_counter() - s0)
+        L.check(st, "latency solve")
+    lat_host = []
+    if host_lat:
+        xh = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+        for i in range(host_lat):
+            s0 = time.perf_counter()
+            L.check(L.wilson_solve_ex(ctx, g, x, srcs[(warmup + i) % nsrc], nrhs, kap, tl, opts)[0], "solve")
+            xh.copy_(x)
+            lat_host.append(time.perf_counter() - s0)
+    # per-kernel figures from a separate pass with event timing on
+    n_prof = min(steps, 3)
     L.wilson_timing_enable(ctx, True)
     tp0 = time.perf_counter()
     for i in range(n_prof):
-        L.check(L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, opts)[0], "profiled solve")
+        L.check(L.wilson_solve_ex(ctx, g, x, srcs[warmup + i], nrhs, kap, tl, opts)[0], "profiled solve")
     torch.cuda.synchronize()
     prof_total = time.perf_counter() - tp0
     h_ms, h_n, h_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_HOP)
     b_ms, b_n, b_bytes = L.wilson_timing_read(ctx, L.WILSON_KERNEL_BLAS)
     L.wilson_timing_enable(ctx, False)
-    solves = args.steps * nrhs
+    solves = steps * nrhs
     hop_gbs = h_bytes / (h_ms * 1e-3) / 1e9
-    traffic = committed_traffic(args.workload, dslash)
-    roofline = {
-        "bound": "hbm",
-        "kernel": (f"parity hop of D_clov (T x - kappa H x), {sname} spinors, {list(dims)}" if clover else
-                   f"parity hop (Dslash D_eo = -kappa H_eo), {sname} spinors, {nrhs} RHS, {list(dims)}"),
-        "achieved": d_gbs,
-        "peak": counts.MI355X_HBM_GBS,
-        "unit": "GB/s",
-        "frac": d_gbs / counts.MI355X_HBM_GBS,
-        "traffic": traffic,
-        "algorithmic_bytes_per_launch": dslash["algorithmic_bytes_per_launch"],
-        "us_per_launch": d_us,
-        "frac_of_copy_bw": d_gbs / copy_gbs,
-        "frac_of_read_bw": d_gbs / read_gbs,
-    }
     solve_hops = {
         "launches": h_n,
         "us_per_launch": 1e3 * h_ms / max(h_n, 1),
@@ -711,11 +768,10 @@ def main():
         "blas_time_fraction": b_ms / (prof_total * 1e3),
     }
 
-    # ---- batched workloads: the same right-hand sides solved one at a time ----
-    sequential = None
-    if nrhs > 1:
+    sequential = fp64_same = lockstep = None
+    if compare and nrhs > 1 and name not in BLOCK:  # the same right-hand sides one at a time
         seq_t = []
-        for i in range(min(args.steps, 3)):
+        for i in range(min(steps, 3)):
             s0 = time.perf_counter()
             for k in range(nrhs):
                 xk = torch.zeros_like(srcs[0][k])
@@ -727,19 +783,16 @@ def main():
         sequential = {"value": nrhs / float(np.median(seq_t)), "unit": "solves/s",
                       "ms_per_batch": 1e3 * float(np.median(seq_t)),
                       "speedup_of_batched": (solves / total) / (nrhs / float(np.median(seq_t)))}
-
-    # ---- reduced-precision workloads: the same problem with the plain FP64 solver ----
-    fp64_same = None
-    if precision != 0:
+    if compare and precision != 0:  # the same problem with the plain FP64 solver
         f_lat, f_it = [], []
         fopts = dict(opts, precision=0, mixed_update=0)
         x.zero_()
         L.check(L.wilson_solve_ex(ctx, g, x, srcs[0], nrhs, kap, tl, fopts)[0], "FP64 warm-up solve")
         torch.cuda.synchronize()
-        nref = min(args.steps, 5)
+        nref = max(min(steps, 5), 2)
         for i in range(nref):
             s0 = time.perf_counter()
-            st, info = L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, fopts)
+            st, info = L.wilson_solve_ex(ctx, g, x, srcs[(warmup + i) % nsrc], nrhs, kap, tl, fopts)
             f_lat.append(time.perf_counter() - s0)
             L.check(st, "FP64 solve")
             f_it.append(max(d["iterations"] for d in info))
@@ -748,20 +801,16 @@ def main():
                      "p99_ms": 1e3 * percentile(f_lat, 99), "iterations_median": float(np.median(f_it)),
                      "solves": nref, "gain_solves_per_s": (solves / total) / f_val,
                      "gain_p99": percentile(f_lat, 99) / percentile(lat, 99)}
-
-    # ---- block workloads: the same batch with one BiCGStab recurrence per right-hand side
-    # (all of them in the same launches) ----
-    lockstep = None
-    if args.workload in BLOCK:
+    if compare and name in BLOCK:  # one BiCGStab recurrence per right-hand side, shared launches
         l_lat, l_it = [], []
         lopts = dict(opts, solver=L.WILSON_SOLVER_BICGSTAB_EO)
         x.zero_()
         L.check(L.wilson_solve_ex(ctx, g, x, srcs[0], nrhs, kap, tl, lopts)[0], "lockstep warm-up solve")
         torch.cuda.synchronize()
-        nref = min(args.steps, 5)
+        nref = max(min(steps, 5), 2)
         for i in range(nref):
             s0 = time.perf_counter()
-            st, info = L.wilson_solve_ex(ctx, g, x, srcs[args.warmup + i], nrhs, kap, tl, lopts)
+            st, info = L.wilson_solve_ex(ctx, g, x, srcs[(warmup + i) % nsrc], nrhs, kap, tl, lopts)
             l_lat.append(time.perf_counter() - s0)
             L.check(st, "lockstep solve")
             l_it.append(max(d["iterations"] for d in info))
@@ -771,55 +820,136 @@ def main():
                     "gain_of_block": (solves / total) / l_val,
                     "iteration_ratio": float(np.median(l_it)) / float(np.median(iters))}
 
-    # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
-    if not args.no_cpu:
-        # the last timed solution and one operator application, graded by the oracle
-        j = args.warmup + args.steps - 1
-        xr = x_last
+    if with_cpu:
+        j = warmup + steps - 1
         xbr = (srcs[j][0] if nrhs > 1 else srcs[j]).cpu().numpy()
-        din = xbr
         gpar = 2 if nrhs > 1 else dpar  # a point source has one parity: grade the full D on it
         dout_t = torch.zeros_like(srcs[j][0] if nrhs > 1 else srcs[j])
         L.check(L.wilson_dslash_ex(ctx, g, dout_t, srcs[j][0].contiguous() if nrhs > 1 else srcs[j], kappa, gpar,
                                    dprec, 1), "graded dslash")
         dout = dout_t.cpu().numpy()
-        cpu = cpu_baseline(args, U, srcs[0], kappa, dims, nrhs, precision, float(np.median(iters)), F,
-                           check=(xr, xbr, dout, din, gpar), block=args.workload in BLOCK)
+        cpu = cpu_baseline(args, U, srcs[0], kappa, tol, dims, nrhs, precision, float(np.median(iters)), F,
+                           check=(x_last, xbr, dout, xbr, gpar), block=name in BLOCK)
+    L.wilson_gauge_free(ctx, g)
+    L.wilson_context_destroy(ctx)
+    del U, srcs, x, F
+    torch.cuda.empty_cache()
+    return {
+        "desc": desc, "dims": list(dims), "kappa": kappa, "tol": tol, "nrhs": nrhs, "precision": precision,
+        "value": solves / total, "unit": "solves/s", "ms_per_step": 1e3 * total / steps, "steps": steps,
+        "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99), "latency_samples": len(lat),
+        "p50_to_host_ms": 1e3 * percentile(lat_host, 50) if lat_host else None,
+        "p99_to_host_ms": 1e3 * percentile(lat_host, 99) if lat_host else None,
+        "latency_to_host_samples": len(lat_host),
+        "iterations_median": float(np.median(iters)), "outer_cycles_median": float(np.median(cycles)),
+        "true_residual_max": max(res), "dslash": dslash, "roofline": roofline, "solve_hops": solve_hops,
+        "cpu_baseline": cpu, "sequential_single_rhs": sequential, "fp64_same_problem": fp64_same,
+        "lockstep_same_batch": lockstep, "setup_s": setup_s,
+    }
 
+
+# Configurations reported beside the headline (C2) in the default run: the small lattice,
+# the three mixed-precision variants at 48^3x96 and the batched point sources.
+EXTRAS = ["small8", "mixed48", "mixed48_fp16", "mixed48_fp16h", "batched24"]
+
+
+def headline(r):
+    """The figures of one configuration that the default line carries as an extra key."""
+    out = {k: r[k] for k in ("desc", "dims", "nrhs", "value", "unit", "p50_ms", "p99_ms", "latency_samples",
+                             "iterations_median", "outer_cycles_median", "true_residual_max")}
+    ro = r["roofline"]
+    out["hop"] = {"us_per_launch": ro["us_per_launch"], "frac": ro["frac"], "frac_floor": ro["frac_floor"],
+                  "frac_counter": ro["frac_counter"], "cache_resident": ro["algorithmic_bytes_per_launch"] < 256e6}
+    if r.get("fp64_same_problem"):
+        f = r["fp64_same_problem"]
+        out["plain_fp64_same_problem"] = {"value": f["value"], "p99_ms": f["p99_ms"],
+                                          "gain_solves_per_s": f["gain_solves_per_s"], "gain_p99": f["gain_p99"]}
+    if r.get("sequential_single_rhs"):
+        out["sequential_single_rhs"] = r["sequential_single_rhs"]
+    if r.get("cpu_baseline"):
+        c = r["cpu_baseline"]
+        out["cpu_oracle"] = {"value": c["value"], "cores": c["cores"], "sample": c["sample"],
+                             "one_core_solve_s": c["one_core"]["solve_s"]}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (see the design notes on "
+              "how the lattice would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    # the oracle's OpenMP threads, one per core, placed close (read when its runtime starts)
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    os.environ.setdefault("OMP_PLACES", "cores")
+    if args.workload == "serve":
+        print(json.dumps(run_serving(args)), flush=True)
+        return
+    if args.workload == "layouts":
+        print(json.dumps(run_layouts(args)), flush=True)
+        return
+    import torch
+
+    from paper_1811_00893_amd import _lib as L
+    r = measure(args, args.workload, args.steps, args.warmup, args.latency_samples, args.dslash_reps,
+                with_cpu=not args.no_cpu and not args.dslash_only, host_lat=20)
+    ctx = L.wilson_context_create()
+    copy_gbs, read_gbs = probes(L, ctx, torch.device("cuda:0"))
+    L.wilson_context_destroy(ctx)
+    r["dslash"]["frac_of_copy_bw"] = r["dslash"]["gbs"] / copy_gbs
+    r["roofline"]["frac_of_copy_bw"] = r["dslash"]["gbs"] / copy_gbs
+    r["roofline"]["frac_of_read_bw"] = r["dslash"]["gbs"] / read_gbs
+    if args.dslash_only:
+        print(json.dumps({"dslash": r["dslash"], "roofline": r["roofline"], "hbm_copy_gbs": copy_gbs,
+                          "hbm_read_gbs": read_gbs}), flush=True)
+        return
+    configs = {}
+    if args.workload == "fp64_32" and not args.no_extras:
+        for name in EXTRAS:
+            small = name == "small8"
+            print(f"[bench] configuration {name}", file=sys.stderr, flush=True)
+            e = measure(args, name, 100 if small else 10, 2, 100 if small else args.extra_latency_samples,
+                        20, with_cpu=small and not args.no_cpu, full_d=False)
+            configs[name] = headline(e)
     line = {
         "metric": METRIC,
-        "value": solves / total,
+        "value": r["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == 0 else "f64/f32",
+        "dtype": "f64" if r["precision"] == 0 else "f64/f32",
         "data": "synthetic",
-        "config": {"workload": desc, "lattice": list(dims), "kappa": kappa, "tol": tol, "eps": 0.3,
-                   "nrhs": nrhs, "precision": ["fp64", "mixed_fp32", "mixed_fp16", "mixed_fp16_l32"][precision]},
-        "p50_ms": 1e3 * percentile(lat, 50),
-        "p99_ms": 1e3 * percentile(lat, 99),
-        "iterations_median": float(np.median(iters)),
-        "outer_cycles_median": float(np.median(cycles)),
-        "true_residual_max": max(res),
-        "dslash": dslash,
-        "roofline": roofline,
-        "solve_hops": solve_hops,
-        "cpu_baseline": cpu,
-        "sequential_single_rhs": sequential,
-        "fp64_same_problem": fp64_same,
-        "lockstep_same_batch": lockstep,
+        "config": {"workload": r["desc"], "lattice": r["dims"], "kappa": r["kappa"], "tol": r["tol"], "eps": 0.3,
+                   "nrhs": r["nrhs"],
+                   "precision": ["fp64", "mixed_fp32", "mixed_fp16", "mixed_fp16_l32"][r["precision"]]},
+        "p50_ms": r["p50_ms"],
+        "p99_ms": r["p99_ms"],
+        "latency_samples": r["latency_samples"],
+        "latency_note": "p50/p99: separate pass, each call timed alone (solution in HBM when it returns); "
+                        "*_to_host_ms: the same plus the copy of x to pinned host memory",
+        "p50_to_host_ms": r["p50_to_host_ms"],
+        "p99_to_host_ms": r["p99_to_host_ms"],
+        "iterations_median": r["iterations_median"],
+        "outer_cycles_median": r["outer_cycles_median"],
+        "true_residual_max": r["true_residual_max"],
+        "dslash": r["dslash"],
+        "roofline": r["roofline"],
+        "solve_hops": r["solve_hops"],
+        "cpu_baseline": r["cpu_baseline"],
+        "sequential_single_rhs": r["sequential_single_rhs"],
+        "fp64_same_problem": r["fp64_same_problem"],
+        "lockstep_same_batch": r["lockstep_same_batch"],
+        "configs": configs or None,
         "hbm_copy_gbs": copy_gbs,
         "hbm_read_gbs": read_gbs,
-        "setup_s": setup_s,
+        "setup_s": r["setup_s"],
     }
-    L.wilson_gauge_free(ctx, g)
-    L.wilson_context_destroy(ctx)
     print(json.dumps(line), flush=True)
 
 

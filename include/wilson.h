@@ -188,6 +188,11 @@ int wilson_gauge_load(wilson_ctx *ctx, wilson_gauge **g, const double *U, const 
 int wilson_gauge_free(wilson_ctx *ctx, wilson_gauge *g);
 /* Device bytes held by a resident gauge field (links and any clover term). */
 size_t wilson_gauge_bytes(const wilson_gauge *g);
+/* Device bytes wilson_gauge_load would keep for this lattice and `precisions` (WILSON_GAUGE_*
+ * bits; FP64 always), with links stored as link_reals = 18 (full) or 12 (the first two rows,
+ * which wilson_gauge_load uses when every link is SU(3) to 1e-13): for admission before a
+ * field is loaded (18 gives an upper bound).  0 for invalid arguments. */
+size_t wilson_gauge_footprint_bytes(const int32_t dims[4], uint32_t precisions, int32_t link_reals);
 
 /*
  * Clover term (Sec. 2.1.2 of the paper): the clover fermion matrix adds a site term,

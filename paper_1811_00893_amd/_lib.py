@@ -40,7 +40,7 @@ EXPORTS = [
     "wilson_batch_create", "wilson_batch_destroy", "wilson_batch_attach", "wilson_batch_step", "wilson_batch_poll",
     "wilson_batch_detach", "wilson_timing_enable", "wilson_timing_read", "wilson_stream_copy", "wilson_strerror",
     "wilson_last_error", "wilson_version", "wilson_stream_read", "wilson_gauge_attach_clover",
-    "wilson_gauge_detach_clover", "wilson_layout_hop", "wilson_solve_noalloc",
+    "wilson_gauge_detach_clover", "wilson_layout_hop", "wilson_solve_noalloc", "wilson_gauge_footprint_bytes",
 ]
 
 
@@ -71,6 +71,7 @@ _SIGS = {
     "wilson_gauge_load": (_i32, [_vp, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_uint32]),
     "wilson_gauge_free": (_i32, [_vp, _vp]),
     "wilson_gauge_bytes": (ctypes.c_size_t, [_vp]),
+    "wilson_gauge_footprint_bytes": (ctypes.c_size_t, [_vp, ctypes.c_uint32, _i32]),
     "wilson_gauge_attach_clover": (_i32, [_vp, _vp, _vp]),
     "wilson_gauge_detach_clover": (_i32, [_vp, _vp]),
     "wilson_dslash_ex": (_i32, [_vp, _vp, _vp, _vp, _d, _i32, _i32, _i32]),
@@ -236,6 +237,11 @@ def wilson_gauge_free(ctx, g):
 
 def wilson_gauge_bytes(g):
     return int(lib().wilson_gauge_bytes(g))
+
+
+def wilson_gauge_footprint_bytes(dims, precisions=WILSON_GAUGE_FP64, link_reals=18):
+    d = _dims(dims)
+    return int(lib().wilson_gauge_footprint_bytes(d.ctypes.data, int(precisions), int(link_reals)))
 
 
 def wilson_gauge_attach_clover(ctx, g, F, dims):

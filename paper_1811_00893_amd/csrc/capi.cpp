@@ -462,6 +462,20 @@ int wilson_solve(double *x, const double *b, const double *U, double kappa, cons
     API_END
 }
 
+size_t wilson_gauge_footprint_bytes(const int32_t dims[4], uint32_t precisions, int32_t link_reals) {
+    try {
+        check_dims(dims);
+        if (link_reals != 12 && link_reals != 18) return 0;
+        const Geom g = make_geom(dims);
+        size_t b = gauge_bytes(P64, link_reals, g);
+        if (precisions & WILSON_GAUGE_FP32) b += gauge_bytes(P32, link_reals, g);
+        if (precisions & WILSON_GAUGE_FP16) b += gauge_bytes(P16, link_reals, g);
+        return b;
+    } catch (...) {
+        return 0;
+    }
+}
+
 size_t wilson_footprint_bytes(const int32_t dims[4], int32_t nrhs, const wilson_solve_opts *opts) {
     try {
         check_dims(dims);

@@ -172,7 +172,8 @@ struct LaunchCfg {
     int wsplit = 0;    // 1: the waves of a block take successive RHS groups of the same 64 sites
     int shx = 0;       // 1: x/y neighbours shuffled from the lanes that loaded them (RPT 1)
     int dsplit = 0;    // 1: five waves per 64-site tile, wave 1 + mu on direction mu (block 320, RPT 1)
-    int ldsl = 0;      // 1: with wsplit, the tile's links loaded once into LDS for all waves of the block
+    int ldsl = 0;      // 1: with wsplit, the tile's links loaded once into LDS for all waves of the block;
+                       // 2: the same with two-row links rebuilt to nine entries while staging
     int tm = 0;        // >= 1: each block marches its segment of the (x,y,z) slices through tm t-slices (every second one)
 };
 

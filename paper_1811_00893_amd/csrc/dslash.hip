@@ -18,8 +18,10 @@ bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c) {
         if (c.zblk != 0 || c.lds_kb != 0 || a.clov_mode != CLV_NONE) return false;
     }
     if (c.ldsl) {  // links in LDS: wave split, one or two RHS per lane, no clover epilogue
-        if (c.ldsl != 1 || !c.wsplit || c.lds_kb != 0 || c.rpt > 2 || (c.shx && c.rpt != 1)) return false;
+        if (c.ldsl < 1 || c.ldsl > 2 || !c.wsplit || c.lds_kb != 0 || c.rpt > 2 || (c.shx && c.rpt != 1)) return false;
         if (a.clov_mode != CLV_NONE || (a.gprec == P64 && a.recon == 18)) return false;
+        // 2: two-row FP32 / FP16 links rebuilt to full links while staging (not with t-marching)
+        if (c.ldsl == 2 && (a.gprec == P64 || a.recon != 12 || c.tm)) return false;
     }
     if (c.rpt < 1 || c.rpt > 4) return false;
     if (c.shx && c.rpt != 1) return false;  // with more RHS per lane the exchange spills

@@ -113,15 +113,18 @@ __device__ __forceinline__ void proj_in(const Cx<real_t<SP>> (&comp)[12], real_t
 // 1 = its projected half spinors given in H.  LL: the link comes from the block's LDS copy
 // `ll` (see stage_links) instead of global memory.
 template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, int MU, bool FWD, int SRC = 0, bool LL = false,
-          int BAR = -1>
+          int BAR = -1, int LNE = 0>
 __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const HopArgs &a, const bool (&act)[RPT],
                                         int r0, int nbr, int link_par, int link_site, real_t<SP> sgn, int stride,
                                         const Cx<real_t<SP>> (*H)[2][3] = nullptr, const char *ll = nullptr) {
     using R = real_t<SP>;
     // link U_mu(x) (forward, at the output site) or U_mu(x - mu) (backward, at the neighbour)
+    // LNE = 9: the block's LDS copy holds all nine entries, the boundary sign folded in
+    constexpr bool FULL = LL && LNE == 9;
     Cx<R> U[3][3];
     {
-        constexpr int NL = LinkElems<GP, NE>::N, CPL = LinkPack<GP>::CPL;
+        constexpr int NEU = FULL ? 9 : NE;
+        constexpr int NL = LinkElems<GP, NEU>::N, CPL = LinkPack<GP>::CPL;
         Cx<R> ue[NL * CPL];
         if constexpr (LL) {
             constexpr int d = 2 * MU + (FWD ? 0 : 1);
@@ -136,9 +139,9 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
                 ld_link_elem<GP, R, LNT>(&ue[e * CPL], lplane<GP>(a.gauge, (link_par * 4 + MU) * NL + e, stride), loff);
         }
 #pragma unroll
-        for (int e = 0; e < NE; e++) U[e / 3][e % 3] = ue[e];
+        for (int e = 0; e < NEU; e++) U[e / 3][e % 3] = ue[e];
     }
-    if constexpr (NE == 6) {
+    if constexpr (NE == 6 && !FULL) {
         // third row of an SU(3) matrix: complex conjugate of (row 0) x (row 1)
         const Cx<R> c0 = csub(cmul(U[0][1], U[1][2]), cmul(U[0][2], U[1][1]));
         const Cx<R> c1 = csub(cmul(U[0][2], U[1][0]), cmul(U[0][0], U[1][2]));
@@ -188,7 +191,7 @@ __device__ __forceinline__ void hop_dir(Cx<real_t<SP>> (&acc)[RPT][4][3], const 
                     if constexpr (FWD) t = cfma(t, U[a_][b_], h[k][b_]);       // U h
                     else               t = cfma_conj(t, U[b_][a_], h[k][b_]);  // U^dag h
                 }
-                u[k][a_] = NE == 6 && MU == 3 ? cscale(t, sgn) : t;
+                u[k][a_] = NE == 6 && MU == 3 && !FULL ? cscale(t, sgn) : t;
             }
         reconstruct<MU, FWD, R>(acc[r], u);
     }
@@ -347,7 +350,59 @@ __device__ __forceinline__ void stage_links(char *ll, const HopArgs &a, int par,
     __syncthreads();
 }
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV, bool LL = false>
+// The same staging with the links stored as two rows: the staging waves rebuild the third
+// row (once per link and block, not once per RHS group) and fold in the antiperiodic sign
+// of the t-links on the slice t = Lt - 1 (lsgn), so the LDS copy holds full links of nine
+// entries (FP32 / FP16: five elements of two complex, the last half unused).
+template <int GP>
+__device__ __forceinline__ void stage_links_full(char *ll, const HopArgs &a, int par, const int (&lsite)[8],
+                                                 const float (&lsgn)[8], int stride) {
+    using R = float;  // FP32 and FP16 links (FP64 links keep the stored form)
+    constexpr int NL6 = LinkElems<GP, 6>::N, NL9 = LinkElems<GP, 9>::N, CPL = LinkPack<GP>::CPL;
+    constexpr unsigned EB = LinkPack<GP>::EB;
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
+    for (int d = w; d < 8; d += nw) {
+        const int mu = d >> 1, lpar = (d & 1) ? 1 - par : par;
+        Cx<R> ue[NL9 * CPL];
+        const unsigned loff = (unsigned)lsite[d] * EB;
+#pragma unroll
+        for (int e = 0; e < NL6; e++)
+            ld_link_elem<GP, R, false>(&ue[e * CPL], lplane<GP>(a.gauge, (lpar * 4 + mu) * NL6 + e, stride), loff);
+        // third row of an SU(3) matrix: complex conjugate of (row 0) x (row 1)
+        const Cx<R> c0 = csub(cmul(ue[1], ue[5]), cmul(ue[2], ue[4]));
+        const Cx<R> c1 = csub(cmul(ue[2], ue[3]), cmul(ue[0], ue[5]));
+        const Cx<R> c2 = csub(cmul(ue[0], ue[4]), cmul(ue[1], ue[3]));
+        ue[6] = {c0.re, -c0.im};
+        ue[7] = {c1.re, -c1.im};
+        ue[8] = {c2.re, -c2.im};
+        if constexpr (NL9 * CPL > 9) ue[9] = {R(0), R(0)};
+        const R sg = (R)lsgn[d];
+#pragma unroll
+        for (int k = 0; k < 9; k++) ue[k] = cscale(ue[k], sg);
+#pragma unroll
+        for (int e = 0; e < NL9; e++) {
+            char *dst = ll + ((unsigned)(d * NL9 + e) * 64u + lane) * EB;
+            if constexpr (GP == P32) {
+                fvec4 v;
+                v.x = ue[2 * e].re;
+                v.y = ue[2 * e].im;
+                v.z = ue[2 * e + 1].re;
+                v.w = ue[2 * e + 1].im;
+                *reinterpret_cast<fvec4 *>(dst) = v;
+            } else {
+                hvec4 v;
+                v[0] = (_Float16)ue[2 * e].re;
+                v[1] = (_Float16)ue[2 * e].im;
+                v[2] = (_Float16)ue[2 * e + 1].re;
+                v[3] = (_Float16)ue[2 * e + 1].im;
+                *reinterpret_cast<hvec4 *>(dst) = v;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV, bool LL = false, int LNE = 0>
 __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, int r0, const bool (&act)[RPT],
                                          double (&red)[RPT][3]) {
     using R = real_t<SP>;
@@ -367,9 +422,15 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
 
     const char *ll = nullptr;
     if constexpr (LL) {
-        __shared__ __align__(16) char ll_buf[8 * LinkElems<GP, NE>::N * 64 * LinkPack<GP>::EB];
+        constexpr int NES = LNE == 9 ? 9 : NE;
+        __shared__ __align__(16) char ll_buf[8 * LinkElems<GP, NES>::N * 64 * LinkPack<GP>::EB];
         const int lsite[8] = {i, xm, i, ym, i, zm, i, tm};
-        stage_links<GP, NE>(ll_buf, a, par, lsite, stride);
+        if constexpr (LNE == 9) {
+            const float lsgn[8] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, c.t == g.L[3] - 1 ? -1.f : 1.f, c.t == 0 ? -1.f : 1.f};
+            stage_links_full<GP>(ll_buf, a, par, lsite, lsgn, stride);
+        } else {
+            stage_links<GP, NE>(ll_buf, a, par, lsite, stride);
+        }
         ll = ll_buf;
         bool any = false;
 #pragma unroll
@@ -396,23 +457,23 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
         load_raw<SP, RPT>(C, Cs, a, act, r0, i, stride);
         Cx<R> H[RPT][2][3];
         lane_nbr<SP, RPT, 0, true, G5>(H, C, Cs, a, act, r0, i, xp, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 1, LL>(acc, a, act, r0, xp, par, i, one, stride, H, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 1, LL, -1, LNE>(acc, a, act, r0, xp, par, i, one, stride, H, ll);
         lane_nbr<SP, RPT, 0, false, G5>(H, C, Cs, a, act, r0, i, xm, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 1, LL>(acc, a, act, r0, xm, opar, xm, one, stride, H, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 1, LL, -1, LNE>(acc, a, act, r0, xm, opar, xm, one, stride, H, ll);
         lane_nbr<SP, RPT, 1, true, G5>(H, C, Cs, a, act, r0, i, yp, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 1, LL>(acc, a, act, r0, yp, par, i, one, stride, H, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 1, LL, -1, LNE>(acc, a, act, r0, yp, par, i, one, stride, H, ll);
         lane_nbr<SP, RPT, 1, false, G5>(H, C, Cs, a, act, r0, i, ym, stride);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 1, LL>(acc, a, act, r0, ym, opar, ym, one, stride, H, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 1, LL, -1, LNE>(acc, a, act, r0, ym, opar, ym, one, stride, H, ll);
     } else {
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 0, LL>(acc, a, act, r0, xp, par, i, one, stride, nullptr, ll);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 0, LL>(acc, a, act, r0, xm, opar, xm, one, stride, nullptr, ll);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 0, LL>(acc, a, act, r0, yp, par, i, one, stride, nullptr, ll);
-        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 0, LL>(acc, a, act, r0, ym, opar, ym, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, true, 0, LL, -1, LNE>(acc, a, act, r0, xp, par, i, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 0, false, 0, LL, -1, LNE>(acc, a, act, r0, xm, opar, xm, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, true, 0, LL, -1, LNE>(acc, a, act, r0, yp, par, i, one, stride, nullptr, ll);
+        hop_dir<SP, GP, RPT, NE, G5, LNT, 1, false, 0, LL, -1, LNE>(acc, a, act, r0, ym, opar, ym, one, stride, nullptr, ll);
     }
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true, 0, LL>(acc, a, act, r0, zp, par, i, one, stride, nullptr, ll);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false, 0, LL>(acc, a, act, r0, zm, opar, zm, one, stride, nullptr, ll);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true, 0, LL>(acc, a, act, r0, tp, par, i, sgn_tf, stride, nullptr, ll);
-    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false, 0, LL>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, true, 0, LL, -1, LNE>(acc, a, act, r0, zp, par, i, one, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 2, false, 0, LL, -1, LNE>(acc, a, act, r0, zm, opar, zm, one, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, true, 0, LL, -1, LNE>(acc, a, act, r0, tp, par, i, sgn_tf, stride, nullptr, ll);
+    hop_dir<SP, GP, RPT, NE, G5, LNT, 3, false, 0, LL, -1, LNE>(acc, a, act, r0, tm, opar, tm, sgn_tb, stride, nullptr, ll);
 
 #pragma unroll
     for (int r = 0; r < RPT; r++) {
@@ -439,7 +500,7 @@ struct HopOcc {
     static constexpr int value = SP == P64 ? 2 : (RPT <= 2 ? 4 : 3);
 };
 
-template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV, bool LL = false>
+template <int SP, int GP, int RPT, int NE, bool G5, bool LNT, bool SHX, bool CLV, bool LL = false, int LNE = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<SP, RPT>::value)))
 hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
     const Geom &g = a.g;
@@ -473,7 +534,7 @@ hop_kernel(const HopArgs a, int xcd_remap, const VisitOrder vo, int wsplit) {
 
     const bool valid = l < g.Vh;
     const int i = valid ? visit_order(l, g, vo) : g.Vh - 1;
-    hop_site<SP, GP, RPT, NE, G5, LNT, SHX, CLV, LL>(a, i, valid, r0, act, red);
+    hop_site<SP, GP, RPT, NE, G5, LNT, SHX, CLV, LL, LNE>(a, i, valid, r0, act, red);
     if (LL && !any) return;
 
     const int nv = red_nvals(a.red);
@@ -868,6 +929,21 @@ static hipError_t launch_hop_ll(const HopArgs &a, const LaunchCfg &c, hipStream_
         vo.per_zb = make_fastdiv((uint32_t)(c.zblk * a.g.L[3]));
         vo.zb = make_fastdiv((uint32_t)c.zblk);
     }
+    if (c.ldsl == 2) {  // two-row links rebuilt to full links while staging (FP32 / FP16 links)
+        if constexpr (NE == 6 && GP != P64) {
+            if (c.rpt == 1)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, false, SHX, false, true, 9>), grid, block, 0, s, a,
+                                   c.xcd, vo, 1);
+            else if (c.rpt == 2 && !SHX)
+                hipLaunchKernelGGL((hop_kernel<SP, GP, 2, NE, G5, false, false, false, true, 9>), grid, block, 0, s, a,
+                                   c.xcd, vo, 1);
+            else
+                return hipErrorInvalidValue;
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (c.rpt == 1)
         hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, false, SHX, false, true>), grid, block, 0, s, a, c.xcd, vo, 1);
     else if (c.rpt == 2 && !SHX)
@@ -883,6 +959,7 @@ template <int SP, int GP, int NE, bool G5>
 static hipError_t launch_hop_t(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const bool lnt = a.nrhs == c.rpt;
     if (c.tm) {
+        if (c.ldsl == 2) return hipErrorInvalidValue;
         if (c.ldsl) {
             if constexpr (GP == P64 && NE == 9) return hipErrorInvalidValue;
             else return c.shx ? launch_hop_tm<SP, GP, NE, G5, false, true, true>(a, c, s)

@@ -282,19 +282,20 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
                             c.shx = shx;
                             if (hop_cfg_valid(a, c)) cands.push_back(c);
                         }
-    for (int block : {128, 192, 256})  // the wave split with the tile's links in LDS
-        for (int rpt : {1, 2})
-            for (int shx : {0, 1})
-                for (int zblk : {0, 4, 8}) {
-                    LaunchCfg c;
-                    c.block = block;
-                    c.rpt = rpt;
-                    c.zblk = zblk;
-                    c.wsplit = 1;
-                    c.shx = shx;
-                    c.ldsl = 1;
-                    if (a.nrhs > 1 && hop_cfg_valid(a, c)) cands.push_back(c);
-                }
+    for (int ldsl : {1, 2})  // the wave split with the tile's links in LDS (2: rebuilt to full links)
+        for (int block : {128, 192, 256})
+            for (int rpt : {1, 2})
+                for (int shx : {0, 1})
+                    for (int zblk : {0, 4, 8}) {
+                        LaunchCfg c;
+                        c.block = block;
+                        c.rpt = rpt;
+                        c.zblk = zblk;
+                        c.wsplit = 1;
+                        c.shx = shx;
+                        c.ldsl = ldsl;
+                        if (a.nrhs > 1 && hop_cfg_valid(a, c)) cands.push_back(c);
+                    }
     // t-marching over 2, 4 or 8 slices: direct links (one or all RHS groups per block) or, with
     // the wave split, links staged in LDS per step
     for (int tm : {2, 4, 8})

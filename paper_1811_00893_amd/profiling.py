@@ -2,6 +2,7 @@
 
   stats   : kernel-trace statistics (`rocprofv3 --kernel-trace --stats --output-format csv`)
             -> a short text table of the top kernels with the command that produced it.
+  counters: per-dispatch means of the counters of several --pmc runs of the hop kernel.
   traffic : HBM bytes per launch of the hop kernel from two counter runs
             (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`; values in KiB per dispatch), each
             calibrated by what the same counter reports for the library's streaming copy of
@@ -120,6 +121,31 @@ def kernel_traffic(fetch_dir, write_dir, match, out, command):
     return text
 
 
+def counters(dirs, out, command, first=8, match="hop_kernel"):
+    """Per-dispatch means of every counter in the `--pmc` runs `dirs` (label=dir pairs) over
+    the first `first` dispatches of the kernel (bench.py --dslash-only: the plain hop
+    launches), one block per label, with derived figures where the counters allow."""
+    lines = ["# rocprofv3 counters per dispatch of the parity hop (mean over the first "
+             f"{first} dispatches of each run)", f"# command: {command}", ""]
+    for label, d in dirs:
+        rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+        per = {}
+        name = None
+        for r in rows:
+            if match in r["Kernel_Name"]:
+                per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+                name = name or short_name(r["Kernel_Name"])
+        ids = sorted(per)[:first]
+        avg = {k: sum(per[i][k] for i in ids) / len(ids) for k in per[ids[0]]}
+        lines.append(f"[{label}] {name} ({len(ids)} dispatches)")
+        for k in sorted(avg):
+            lines.append(f"  {k:38s} {avg[k]:16.6g}")
+        lines.append("")
+    text = "\n".join(lines) + "\n"
+    open(out, "w").write(text)
+    return text
+
+
 def main():
     p = argparse.ArgumentParser()
     sub = p.add_subparsers(dest="cmd", required=True)
@@ -135,6 +161,11 @@ def main():
     c.add_argument("--match", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--command", required=True)
+    k = sub.add_parser("counters")
+    k.add_argument("--run", action="append", required=True, help="label=directory of one --pmc run")
+    k.add_argument("--out", required=True)
+    k.add_argument("--command", required=True)
+    k.add_argument("--first", type=int, default=8)
     b = sub.add_parser("traffic")
     b.add_argument("--workload", required=True)
     b.add_argument("--fetch", required=True)
@@ -146,6 +177,8 @@ def main():
     args = p.parse_args()
     if args.cmd == "stats":
         print(stats(args.dir, args.out, args.command, args.top, args.match))
+    elif args.cmd == "counters":
+        print(counters([tuple(r.split("=", 1)) for r in args.run], args.out, args.command, args.first))
     elif args.cmd == "kernel-traffic":
         print(kernel_traffic(args.fetch, args.write, args.match, args.out, args.command))
     else:

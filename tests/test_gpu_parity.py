@@ -221,7 +221,8 @@ def test_batched_point_sources(L, ctx):
 
 @pytest.mark.parametrize("cfg", ["256,1,1,0,0,1", "192,2,1,4,0,1", "128,3,1,0,0,1", "320,1,1,0,0,0,0,1",
                                  "256,1,1,4,0,1,1,0,1", "128,2,1,0,0,1,0,0,1",
-                                 "256,1,1,0,0,1,1,0,1,2", "128,3,1,0,0,1,0,0,0,4", "64,2,1,0,0,0,0,0,0,1"])
+                                 "256,1,1,0,0,1,1,0,1,2", "128,3,1,0,0,1,0,0,0,4", "64,2,1,0,0,0,0,0,0,1",
+                                 "256,1,1,0,0,1,1,0,2", "128,2,1,0,0,1,0,0,2"])
 def test_batched_solve_wave_split_configs(L, cfg, monkeypatch):
     """The batched solve with the hop's RHS groups split over the waves of a block (each
     wave writes its own partial sums of the fused reductions; also with the tile's links
@@ -352,7 +353,10 @@ def test_full_size_sampled_dslash(L, ctx):
                                  # lane, lane exchange, wave split with links in LDS, wave split
                                  # in plain block order, four RHS per lane (FP64: two)
                                  "64,1,1,0,0,0,0,0,0,5", "128,2,1,0,0,0,0,0,0,1", "64,1,1,0,0,0,1,0,0,5",
-                                 "256,1,1,0,0,1,1,0,1,5", "128,1,0,0,0,1,0,0,0,1", "64,4,1,0,0,0,0,0,0,5"])
+                                 "256,1,1,0,0,1,1,0,1,5", "128,1,0,0,0,1,0,0,0,1", "64,4,1,0,0,0,0,0,0,5",
+                                 # links rebuilt to nine entries while staged in LDS (FP32 links;
+                                 # FP64 falls back to the stored form)
+                                 "256,1,1,0,0,1,1,0,2", "128,2,1,2,0,1,0,0,2"])
 def test_dslash_every_launch_config(L, cfg, monkeypatch):
     """Every hop launch configuration the tuner can pick (block size, RHS per thread,
     XCD tile order, plane-blocked visiting order, LDS cap, RHS groups split over the
@@ -369,9 +373,9 @@ def test_dslash_every_launch_config(L, cfg, monkeypatch):
     nrhs = 4
     psi = inputs.gaussian_source(dims, seed=31, nrhs=nrhs)
     c = L.wilson_context_create()
-    g = L.wilson_gauge_load(c, U.to(DEV), dims, L.WILSON_GAUGE_FP32)
+    g = L.wilson_gauge_load(c, U.to(DEV), dims, L.WILSON_GAUGE_FP32 | L.WILSON_GAUGE_FP16)
     try:
-        for prec, lim in ((0, 1e-12), (1, 5e-7)):
+        for prec, lim in ((0, 1e-12), (1, 5e-7), (2, 2e-3)):
             out = torch.zeros_like(psi, device=DEV)
             L.check(L.wilson_dslash_ex(c, g, out, psi.to(DEV), 0.125, 2, prec, nrhs), "dslash")
             for k in range(nrhs):

@@ -115,3 +115,41 @@ def test_batch_api_slot_lifecycle():
     L.wilson_batch_destroy(bat)
     L.wilson_gauge_free(ctx, g)
     L.wilson_context_destroy(ctx)
+
+
+def test_evicted_and_reloaded_field_gives_identical_results():
+    """An HBM budget with room for one 8^4 field and its batch but not two fields: requests on
+    fields a, b, a load a, release it for b, and load it again (then b is released).  The
+    third request (field a, the same sources and kappa as the first) gives bitwise the
+    first one's solutions, every result passes the oracle, and solutions arrive on the host
+    through the engine's asynchronous copy."""
+    from paper_1811_00893_amd.serve import LibEngine, Scheduler
+    dims = (8, 8, 8, 8)
+    Ua = inputs.gauge_field(dims, eps=0.3, seed=1601)
+    Ub = inputs.gauge_field(dims, eps=0.25, seed=1602)
+    b = inputs.gaussian_source(dims, seed=1603, nrhs=2)
+    eng = LibEngine(precision=1, host_results=True)
+    ga = eng.add_gauge_source("a", Ua.cuda(), dims)
+    gb = eng.add_gauge_source("b", lambda: Ub.cuda(), dims)  # a source may also be produced on demand
+    bb = eng.batch_bytes(dims, 2)
+    sch = Scheduler(eng, ga + bb + ga // 4, nslots=2, step_iters=4)
+    sch.register_gauge("a", dims, ga, resident=False)
+    sch.register_gauge("b", dims, gb, resident=False)
+    reqs = [Request(rid=k, gauge_id=g, kappa=0.12, tol=1e-10, b=b.clone()) for k, g in enumerate("aba")]
+    try:
+        for r in reqs:
+            assert sch.submit(r)
+            sch.run_until_idle()
+            assert sch.resident_bytes() <= sch.budget
+    finally:
+        sch.close()
+        eng.close()
+    print(f"loads {sch.loads}, evictions {sch.evictions}")
+    assert sch.loads == 3 and sch.evictions == 2
+    assert [r.rid for r in sch.completed] == [0, 1, 2]
+    assert not reqs[0].x.is_cuda and not reqs[2].x.is_cuda
+    assert torch.equal(reqs[0].x, reqs[2].x)
+    for r, U in zip(reqs, (Ua, Ub, Ua)):
+        for j in range(2):
+            assert r.status[j] == 0
+            assert residual(r.x[j].numpy(), b[j].numpy(), U.numpy(), 0.12, dims) < 1e-10

@@ -266,3 +266,65 @@ def test_heavy_batches_take_turns_oldest_first():
     assert sorted(r.rid for r in sch.completed) == [0, 1, 2]
     with pytest.raises(ValueError):
         Scheduler(eng, hbm_budget=1e9, max_heavy=0)
+
+
+class LoadingEngine(FakeEngine):
+    """FakeEngine whose gauge fields are loaded and unloaded on demand (40 bytes each)."""
+
+    def __init__(self, batch_bytes=100.0):
+        super().__init__(batch_bytes)
+        self.loaded = set()
+        self.log = []
+
+    def load_gauge(self, gid):
+        assert gid not in self.loaded
+        self.loaded.add(gid)
+        self.log.append(("load", gid))
+        return 40
+
+    def unload_gauge(self, gid):
+        assert not any(h[0] == gid for h in self.batches), "field unloaded under a live batch"
+        self.loaded.remove(gid)
+        self.log.append(("unload", gid))
+
+    def create_batch(self, gid, nslots):
+        assert gid in self.loaded, "batch on a field that is not resident"
+        return super().create_batch(gid, nslots)
+
+
+def test_gauge_fields_load_on_demand_and_evict_least_recently_used():
+    """With room for one field and its batch (170 < 2 x 40 + 100), requests on fields a, b, a
+    load a, then release
+    a's idle batch and field for b, then reload a; the loaded size replaces the upper bound,
+    and no request is rejected."""
+    eng = LoadingEngine(batch_bytes=100)
+    sch = Scheduler(eng, hbm_budget=170, nslots=2, step_iters=50, clock=Clock())
+    for g in "ab":
+        sch.register_gauge(g, (4, 4, 4, 4), 50, resident=False)  # 50: upper bound; 40 once loaded
+    for rid, g in enumerate("aba"):
+        assert sch.submit(mkreq(rid, g, 1))
+        sch.run_until_idle()
+        assert sch.resident_bytes() <= 170
+    assert eng.log == [("load", "a"), ("unload", "a"), ("load", "b"), ("unload", "b"), ("load", "a")]
+    assert sch.loads == 3 and sch.evictions == 2
+    assert sch.gauges["a"]["bytes"] == 40 and sch.gauges["a"]["resident"]
+    assert [r.rid for r in sch.completed] == [0, 1, 2]
+    assert list(sch.completed[2].x[:, 0]) == [200]
+
+
+def test_field_with_an_older_waiting_request_is_not_evicted():
+    """A request for field b that arrives while an older request for a still has right-hand
+    sides waiting does not take a's place: a's request finishes first, then b is loaded."""
+    eng = LoadingEngine(batch_bytes=100)
+    sch = Scheduler(eng, hbm_budget=170, nslots=2, step_iters=5, clock=Clock())
+    for g in "ab":
+        sch.register_gauge(g, (4, 4, 4, 4), 40, resident=False)
+    assert sch.submit(mkreq(0, "a", 5))   # 5 RHS through 2 slots: part of it waits
+    assert sch.submit(mkreq(1, "b", 1))
+    sch.run_until_idle()
+    assert [r.rid for r in sch.completed] == [0, 1]
+    assert eng.log == [("load", "a"), ("unload", "a"), ("load", "b")]
+    # a field that can never fit (40 + 100 > 120) is still rejected at once
+    small = Scheduler(LoadingEngine(batch_bytes=100), hbm_budget=120, nslots=2, clock=Clock())
+    small.register_gauge("c", (4, 4, 4, 4), 40, resident=False)
+    assert not small.submit(mkreq(3, "c", 1))
