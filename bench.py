@@ -50,7 +50,8 @@ def parse():
     p.add_argument("--turn-ms", type=float, default=3.0, help="serving: target duration of a scheduler turn")
     p.add_argument("--max-heavy", type=int, default=2,
                    help="serving: heavy batches (an iteration >= 0.5 ms) advancing at once, oldest first (0: no limit)")
-    p.add_argument("--hbm-budget", type=float, default=200e9, help="serving: device bytes for fields + batches")
+    p.add_argument("--hbm-budget", type=float, default=100e9, help="serving: device bytes for fields + batches")
+    p.add_argument("--nslots", type=int, default=12, help="serving: solve slots per gauge field's batch")
     p.add_argument("--latency-samples", type=int, default=100, help="solves of the latency pass (p50/p99)")
     p.add_argument("--extra-latency-samples", type=int, default=30,
                    help="latency pass of the other configurations of the default run (8^4 takes 100)")
@@ -142,7 +143,11 @@ def run_serving(args):
          `--outstanding` requests waiting or running): RHS/s and requests/s.
       3. For each offered load in `--loads` (fractions of that capacity): Poisson arrivals
          at load x capacity replayed through the server; p50/p99 latency (arrival ->
-         solution in device memory) and throughput, next to FIFO on the same arrivals.
+         solution on the host) and throughput, next to FIFO on the same arrivals.
+    Every latency, FIFO's too, ends when the solution is in pinned host memory.  The server
+    admits by HBM footprint within `--hbm-budget`: the gauge fields are registered as
+    sources and loaded when first needed; idle batches and fields are released to make
+    room (least recently used first) and reloaded when needed again.
     """
     import numpy as np
     import torch
@@ -187,6 +192,8 @@ def run_serving(args):
         x = torch.zeros_like(b)
         st, _ = L.wilson_solve_ex(ctx, G[t["gid"]], x, b, t["nrhs"], t["kappa"], t["tol"], opts)
         L.check(st, "fifo solve")
+        xh = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+        xh.copy_(x)  # the solution on the host
 
     # warm the tuner: every lattice size and class of RHS count before anything is timed
     for si, d in enumerate(sizes):
@@ -222,6 +229,8 @@ def run_serving(args):
             x = torch.zeros_like(b[j])
             st, _ = L.wilson_solve_ex(ctx, G[t["gid"]], x, b[j], 1, t["kappa"], t["tol"], popts)
             L.check(st, "plain FP64 solve")
+            xh = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+            xh.copy_(x)
         torch.cuda.synchronize()
         plain.append(time.perf_counter() - s0)
         del b
@@ -233,11 +242,11 @@ def run_serving(args):
     L.wilson_context_destroy(ctx)
 
     # the continuous-batching server
-    sch, eng = make_server(hbm_budget=args.hbm_budget, nslots=12, step_iters=args.step_iters, precision=1,
-                           turn_ms=args.turn_ms, max_heavy=args.max_heavy if args.max_heavy > 0 else None)
-    for gid, (d, e, s) in pool.items():
-        sch.register_gauge(gid, d, eng.load_gauge(gid, U[gid], d))
-    eng.alloc_solution = lambda req: torch.zeros_like(req.b)
+    sch, eng = make_server(hbm_budget=args.hbm_budget, nslots=args.nslots, step_iters=args.step_iters, precision=1,
+                           turn_ms=args.turn_ms, max_heavy=args.max_heavy if args.max_heavy > 0 else None,
+                           host_results=True)
+    for gid, (d, e, s) in pool.items():  # loaded on first use, within the budget
+        sch.register_gauge(gid, d, eng.add_gauge_source(gid, U[gid], d), resident=False)
     for si, d in enumerate(sizes):  # one request per lattice size through the server
         sch.submit(Request(rid=-1 - si, gauge_id=(si, 0), kappa=0.12, tol=1e-8,
                            b=inputs.gaussian_source(d, seed=3950, nrhs=1, device=dev)))
@@ -323,9 +332,11 @@ def run_serving(args):
         "gain_over_plain_fp64": (rhs_total / wall_c) / (rhs_total / plain_total),
         "load_points": points,
         "rejected": len(sch.rejected),
-        "config": {"lattices": sizes, "gauge_fields_per_size": 2, "nslots": 12, "step_iters_max": args.step_iters,
-                   "turn_ms": args.turn_ms, "max_heavy": args.max_heavy,
-                   "precision": "mixed_fp32", "latency": "arrival to solution in device memory",
+        "gauge_loads": sch.loads, "gauge_evictions": sch.evictions,
+        "config": {"lattices": sizes, "gauge_fields_per_size": 2, "nslots": args.nslots,
+                   "step_iters_max": args.step_iters, "turn_ms": args.turn_ms, "max_heavy": args.max_heavy,
+                   "hbm_budget": args.hbm_budget,
+                   "precision": "mixed_fp32", "latency": "arrival to solution in pinned host memory",
                    "loads_relative_to": "closed-loop capacity of the continuous-batching server"},
     }
 
