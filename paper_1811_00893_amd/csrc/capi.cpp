@@ -251,6 +251,8 @@ int wilson_context_destroy(wilson_ctx *ctx) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    ctx->solve_cache.clear();  // their captured graphs first
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return WILSON_OK;
     API_END

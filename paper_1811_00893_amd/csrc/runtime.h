@@ -173,6 +173,7 @@ struct wilson_ctx {
     // the context, so those solves allocate nothing themselves)
     wl::SolveHostRes lend;
     void *scratch = nullptr;         // device address of the no-allocation solve's array on this device
+    hipStream_t capture_stream = nullptr;  // stream that iteration chunks are captured on (HIP graphs)
     bool no_tune = false;            // set for the duration of a call that must not tune
     wl::DevBuf stage_in, stage_out;  // canonical staging for host pointers
     wl::DevBuf flag;                 // device int for finiteness checks

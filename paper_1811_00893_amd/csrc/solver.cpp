@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -45,6 +46,19 @@ static inline int inner_gauge_prec(int precision) {
 }
 
 constexpr int kRing = kStateRing;  // host-mapped state mirrors in flight
+// Iteration chunks captured as HIP graphs: lattices up to this many sites per parity (where
+// the kernels are short and the gaps between launches a large part of an iteration), this
+// many iterations per graph.
+constexpr int kGraphMaxVh = 1 << 16;
+constexpr int kGraphChunk = 4;
+// Graph replay of iteration chunks is opt-in (WILSON_GRAPHS=1, read per solve): on ROCm 7.2
+// a replayed chunk took longer than the same kernels launched one by one (8^4 FP64 solves
+// 1.30 ms against 1.26 ms), since the host already runs ahead of the device and a graph
+// does not shorten the gaps between dependent kernels on the device.
+static bool graphs_enabled() {
+    const char *e = std::getenv("WILSON_GRAPHS");
+    return e && std::strcmp(e, "1") == 0;
+}
 constexpr int kAllPhases = PH_IDLE | PH_RUN | PH_SCONV | PH_DONE | PH_FAIL;
 
 size_t EoMem::carve(char *base, const Geom &g, int n, int precision, int method) {
@@ -94,6 +108,18 @@ class EoCore : public EoMem {
     std::unique_ptr<SolveHostRes> own_host; // host resources, when not lent
     SolveHostRes *host = nullptr;
     const hipEvent_t *ring_ev = nullptr;
+    // captured iteration chunks: one executable graph per solution field, RHS range, kappa
+    // values and mirror slot (the kernels' arguments), with the bookkeeping of one replay
+    bool graphs = false;  // set per call
+    struct Chunk {
+        const void *x;
+        int k0, nk, method, slot, iters;
+        std::vector<double> kappa;
+        hipGraphExec_t exec;
+        int64_t hops;
+        double bytes, flops;
+    };
+    std::vector<Chunk> chunks;
 
     // ws / ws_bytes: the caller's device region (null: allocate one); lent: host resources
     // to use instead of allocating (at least n right-hand sides)
@@ -137,6 +163,9 @@ class EoCore : public EoMem {
         G = gauge;
     }
 
+    ~EoCore() {
+        for (auto &c : chunks) (void)hipGraphExecDestroy(c.exec);
+    }
     size_t footprint() const { return bytes; }
 
     Spinor V(Spinor f) const {
@@ -407,13 +436,22 @@ class EoCore : public EoMem {
         if (!any_run) return init;
         poll_every = std::max(1, poll_every);
         int enq = 0;
-        for (it = 0; it < maxiter; it++) {
-            const bool poll_here = ((it + 1) % poll_every == 0) || it + 1 == maxiter;
+        // with graphs: after one ordinary iteration (which settles every launch shape), chunks
+        // of kGraphChunk iterations replayed from a captured graph, polled at their end; the
+        // device runs the same kernels with the same arguments, so the result is the same
+        const bool chunked = graphs && method != WILSON_SOLVER_BLOCK_BICGSTAB_EO && !ctx->timing;
+        for (it = 0; it < maxiter;) {
             const int slot = enq % kRing;
-            RhsState *mir = poll_here ? mirror_dev(slot) : nullptr;
-            if (method == WILSON_SOLVER_BICGSTAB_EO) bicg_iter(x, mir);
-            else if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) block_iter(x, mir);
-            else cg_iter(x, mir);
+            bool poll_here;
+            if (chunked && it >= 1 && it + kGraphChunk <= maxiter) {
+                replay_chunk(x, slot);
+                it += kGraphChunk;
+                poll_here = true;
+            } else {
+                poll_here = ((it + 1) % poll_every == 0) || it + 1 == maxiter;
+                iterate(x, poll_here ? mirror_dev(slot) : nullptr);
+                it++;
+            }
             if (!poll_here) continue;
             WL_HIP(hipEventRecord(ring_ev[slot], ctx->stream));
             enq++;
@@ -427,6 +465,65 @@ class EoCore : public EoMem {
             }
         }
         return read_states(sin());
+    }
+
+    void iterate(Spinor x, RhsState *mir) {
+        if (method == WILSON_SOLVER_BICGSTAB_EO) bicg_iter(x, mir);
+        else if (method == WILSON_SOLVER_BLOCK_BICGSTAB_EO) block_iter(x, mir);
+        else cg_iter(x, mir);
+    }
+
+    // kGraphChunk iterations from a graph captured on the context's capture stream (kernel
+    // nodes only: the iterations launch nothing else) and replayed on its stream; the last
+    // one writes the state mirror of `slot`.
+    void replay_chunk(Spinor x, int slot) {
+        const std::vector<double> kap(kappa.begin() + k0, kappa.begin() + k0 + nk);
+        Chunk *c = nullptr;
+        for (auto &e : chunks)
+            if (e.x == x.data && e.k0 == k0 && e.nk == nk && e.method == method && e.slot == slot &&
+                e.iters == kGraphChunk && e.kappa == kap) {
+                c = &e;
+                break;
+            }
+        if (!c) {
+            if (!ctx->capture_stream) WL_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+            const int64_t h0 = ctx->hop_launch_count;
+            const double b0 = ctx->bytes_issued, f0 = ctx->flops_issued;
+            hipStream_t run = ctx->stream;
+            hipGraph_t gph = nullptr;
+            ctx->stream = ctx->capture_stream;  // every launch of the iterations goes to the capture
+            WL_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int i = 0; i < kGraphChunk; i++) iterate(x, i == kGraphChunk - 1 ? mirror_dev(slot) : nullptr);
+            } catch (...) {
+                (void)hipStreamEndCapture(ctx->stream, &gph);
+                if (gph) (void)hipGraphDestroy(gph);
+                ctx->stream = run;
+                throw;
+            }
+            const hipError_t e = hipStreamEndCapture(ctx->stream, &gph);
+            ctx->stream = run;
+            WL_HIP(e);
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gph);
+            WL_HIP(ei);
+            if (chunks.size() >= 16) {  // keep the most recent graphs
+                (void)hipGraphExecDestroy(chunks.front().exec);
+                chunks.erase(chunks.begin());
+            }
+            // the capture ran nothing: its bookkeeping belongs to each replay
+            chunks.push_back({x.data, k0, nk, method, slot, kGraphChunk, kap, ex, ctx->hop_launch_count - h0,
+                              ctx->bytes_issued - b0, ctx->flops_issued - f0});
+            ctx->hop_launch_count = h0;
+            ctx->bytes_issued = b0;
+            ctx->flops_issued = f0;
+            c = &chunks.back();
+        }
+        WL_HIP(hipGraphLaunch(c->exec, ctx->stream));
+        ctx->hop_launch_count += c->hops;
+        ctx->bytes_issued += c->bytes;
+        ctx->flops_issued += c->flops;
     }
 
     void bicg_iter(Spinor x, RhsState *mir) {
@@ -573,6 +670,7 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
                               : get_core(ctx, G, nrhs, prm);
     EoCore &C = *core;
     const Geom &g = C.g;
+    C.graphs = prm.graphs && !prm.no_tune && graphs_enabled() && g.Vh <= kGraphMaxVh;
     C.select(0, nrhs);
     C.kappa.assign(C.nrhs, 0.0);
     std::copy(kappa, kappa + nrhs, C.kappa.begin());

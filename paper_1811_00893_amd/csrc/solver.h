@@ -66,6 +66,7 @@ struct SolveParams {
     void *workspace = nullptr;    // device region for every buffer of the solve (null: the library's)
     size_t workspace_bytes = 0;
     bool no_tune = false;         // launch shapes from the tuning table or the defaults, no tuning runs
+    bool graphs = true;           // small lattices may replay iteration chunks as HIP graphs (WILSON_GRAPHS=1)
 };
 
 // Solves for nrhs right-hand sides given in canonical layout on the device.
