@@ -241,6 +241,17 @@ int wilson_solve_ex(wilson_ctx *ctx, const wilson_gauge *g, double *x, const dou
                     const double *kappa, const double *tol, const wilson_solve_opts *opts,
                     wilson_solve_info *info);
 
+/* Host check of the site indexing the kernels use on lattice dims (no device work; the
+ * library's own index functions, compiled for the host, replayed over every site of
+ * both parities): coordinates decoded from every checkerboard index, the eight
+ * neighbour indices of the hop (in range, at the right coordinates, on the other
+ * parity, each direction a permutation), every plane-blocked visiting order and the
+ * XCD-contiguous block order of the launch grids.  Returns WILSON_OK, a negative
+ * error code for invalid dims, or the number of violations (> 0; the first is
+ * described by wilson_last_error()).  Diagnostic: cost O(V) time and 64 bytes per
+ * site of host memory. */
+int wilson_index_check(const int32_t dims[4]);
+
 /* Device bytes wilson_solve_ex would allocate for this lattice, nrhs and options
  * (workspace only; the resident gauge field is wilson_gauge_bytes); also the smallest
  * opts->workspace_bytes a caller-owned workspace may have. */

@@ -41,6 +41,7 @@ EXPORTS = [
     "wilson_batch_detach", "wilson_timing_enable", "wilson_timing_read", "wilson_stream_copy", "wilson_strerror",
     "wilson_last_error", "wilson_version", "wilson_stream_read", "wilson_gauge_attach_clover",
     "wilson_gauge_detach_clover", "wilson_layout_hop", "wilson_solve_noalloc", "wilson_gauge_footprint_bytes",
+    "wilson_index_check",
 ]
 
 
@@ -72,6 +73,7 @@ _SIGS = {
     "wilson_gauge_free": (_i32, [_vp, _vp]),
     "wilson_gauge_bytes": (ctypes.c_size_t, [_vp]),
     "wilson_gauge_footprint_bytes": (ctypes.c_size_t, [_vp, ctypes.c_uint32, _i32]),
+    "wilson_index_check": (_i32, [_vp]),
     "wilson_gauge_attach_clover": (_i32, [_vp, _vp, _vp]),
     "wilson_gauge_detach_clover": (_i32, [_vp, _vp]),
     "wilson_dslash_ex": (_i32, [_vp, _vp, _vp, _vp, _d, _i32, _i32, _i32]),
@@ -237,6 +239,15 @@ def wilson_gauge_free(ctx, g):
 
 def wilson_gauge_bytes(g):
     return int(lib().wilson_gauge_bytes(g))
+
+
+def wilson_index_check(dims):
+    """Host replay of the kernels' site indexing on one lattice: 0, a negative error code,
+    or the number of violations (the first in wilson_last_error())."""
+    if dims is None:
+        return int(lib().wilson_index_check(None))
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    return int(lib().wilson_index_check(d.ctypes.data))
 
 
 def wilson_gauge_footprint_bytes(dims, precisions=WILSON_GAUGE_FP64, link_reals=18):

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libwilson.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["dslash.hip", "dslash_p64.hip", "dslash_p32.hip", "dslash_p16.hip", "dslash_p16l32.hip", "clover.hip", "blas.hip", "block.hip", "layout.hip", "layout_lab.hip", "runtime.cpp", "solver.cpp", "capi.cpp"]
+SOURCES = ["dslash.hip", "dslash_p64.hip", "dslash_p32.hip", "dslash_p16.hip", "dslash_p16l32.hip", "clover.hip", "blas.hip", "block.hip", "layout.hip", "layout_lab.hip", "runtime.cpp", "solver.cpp", "capi.cpp", "indexcheck.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-I", HERE, "-I", os.path.join(ROOT, "include")]
@@ -47,5 +47,57 @@ def build(verbose=False, jobs=8):
     return OUT
 
 
+# The host code (runtime, solver, C ABI, index check) rebuilt with AddressSanitizer and
+# UndefinedBehaviorSanitizer for the CPU tests; device code is never instrumented.
+HOST_SOURCES = ["runtime.cpp", "solver.cpp", "capi.cpp", "indexcheck.cpp"]
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-g"]
+SAN_OUT = os.path.join(BUILD, "san", "libwilson_san.so")
+
+
+def build_sanitized(verbose=False, jobs=4):
+    """_build/san/libwilson_san.so: the host sources compiled with the sanitizers, linked
+    with the device objects of the plain build (built first when missing).  It needs the
+    sanitizer runtime preloaded (sanitizer_runtime()); only the CPU tests load it."""
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    dev_objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES if s not in HOST_SOURCES]
+    if not all(os.path.exists(o) for o in dev_objs):
+        build(verbose)
+
+    def compile_san(src):
+        obj = os.path.join(san, os.path.splitext(src)[0] + ".o")
+        cmd = ["hipcc", "-x", "hip"] + COMMON + DEVICE + SANITIZE + ["-c", os.path.join(HERE, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {src}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_san, HOST_SOURCES))
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", SAN_OUT + ".tmp"] + objs + dev_objs + SANITIZE
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(SAN_OUT + ".tmp", SAN_OUT)
+    return SAN_OUT
+
+
+def sanitizer_runtime():
+    """The compiler's shared AddressSanitizer runtime (it carries the UndefinedBehavior
+    handlers too), for LD_PRELOAD into a process that loads libwilson_san.so."""
+    r = subprocess.run(["hipcc", "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    import glob
+    found = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/*/libclang_rt.asan*.so")
+    return found[0] if found else None
+
+
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        build(verbose="-v" in sys.argv)

@@ -6,6 +6,8 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
+#include <algorithm>
 
 #include "layout_lab.h"
 #include "runtime.h"
@@ -476,6 +478,17 @@ size_t wilson_gauge_footprint_bytes(const int32_t dims[4], uint32_t precisions, 
     } catch (...) {
         return 0;
     }
+}
+
+int wilson_index_check(const int32_t dims[4]) {
+    API_BEGIN
+    check_dims(dims);
+    std::string first;
+    const long long bad = index_check(dims, first);
+    if (bad == 0) return WILSON_OK;
+    set_last_error(std::to_string(bad) + " index violations; first: " + first);
+    return (int)std::min<long long>(bad, 0x7fffffff);
+    API_END
 }
 
 size_t wilson_footprint_bytes(const int32_t dims[4], int32_t nrhs, const wilson_solve_opts *opts) {

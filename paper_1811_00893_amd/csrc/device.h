@@ -379,11 +379,14 @@ __device__ __forceinline__ void wave_reduce_to(double (&v)[NV], double *dst, siz
     }
 }
 
+// Site indexing: shared by the kernels and by the host replay of their index maps
+// (wilson_index_check), so the host checks the code the kernels run.
+//
 // Site coordinates of checkerboard index i on output parity par.
 struct SiteXY {
     int xh, b, y, z, t;
 };
-__device__ __forceinline__ SiteXY cb_coords(const Geom &g, int i, int par) {
+__host__ __device__ __forceinline__ SiteXY cb_coords(const Geom &g, int i, int par) {
     SiteXY c;
     const int q1 = (int)fdiv((uint32_t)i, g.dLxh);   // i / (Lx/2)
     c.xh = i - q1 * g.Lxh;
@@ -393,6 +396,27 @@ __device__ __forceinline__ SiteXY cb_coords(const Geom &g, int i, int par) {
     c.z = q2 - c.t * g.L[2];
     c.b = (c.y + c.z + c.t + par) & 1;  // x = 2*xh + b
     return c;
+}
+
+// Checkerboard indices, in the fields of the other parity, of the eight neighbours of
+// output site i (coordinates c): x+1, x-1, y+1, ..., t-1, periodic in every direction
+// (the antiperiodic t sign is applied by the hop).  Along x the neighbour shares the
+// site's row; whether x+1 is the same checkerboard column or the next depends on b.
+struct SiteNbrs {
+    int xp, xm, yp, ym, zp, zm, tp, tm;
+};
+__host__ __device__ __forceinline__ SiteNbrs site_nbrs(const Geom &g, int i, const SiteXY &c) {
+    SiteNbrs n;
+    const int row = i - c.xh;
+    n.xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
+    n.xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
+    n.yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
+    n.ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
+    n.zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
+    n.zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
+    n.tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
+    n.tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+    return n;
 }
 
 // Processing order of sites.  zblk = 0: memory order (x, y, z, t).  zblk > 0: the
@@ -405,7 +429,17 @@ struct VisitOrder {
     int zblk = 0;
     FastDiv plane, per_zb, zb;  // division by Lxh*Ly, zblk*Lt and zblk
 };
-__device__ __forceinline__ int visit_order(int l, const Geom &g, const VisitOrder &v) {
+inline VisitOrder make_visit_order(const Geom &g, int zblk) {
+    VisitOrder vo;
+    if (zblk > 0) {
+        vo.zblk = zblk;
+        vo.plane = make_fastdiv((uint32_t)(g.Lxh * g.L[1]));
+        vo.per_zb = make_fastdiv((uint32_t)(zblk * g.L[3]));
+        vo.zb = make_fastdiv((uint32_t)zblk);
+    }
+    return vo;
+}
+__host__ __device__ __forceinline__ int visit_order(int l, const Geom &g, const VisitOrder &v) {
     if (v.zblk <= 0) return l;
     const int S = (int)v.plane.d;
     const int pl = (int)fdiv((uint32_t)l, v.plane), within = l - pl * S;
@@ -416,7 +450,7 @@ __device__ __forceinline__ int visit_order(int l, const Geom &g, const VisitOrde
 
 // Block index remapped so that each XCD (blocks are dealt round-robin to 8 XCDs)
 // processes one contiguous range of tiles: neighbouring tiles share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int n) {
+__host__ __device__ __forceinline__ int xcd_tile(int b, int n) {
     const int q = n >> 3, rem = n & 7;
     const int k = b & 7, j = b >> 3;
     return (k < rem) ? k * (q + 1) + j : rem * (q + 1) + (k - rem) * q + j;

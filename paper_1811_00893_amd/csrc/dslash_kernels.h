@@ -410,15 +410,8 @@ __device__ __forceinline__ void hop_site(const HopArgs &a, int i, bool valid, in
     const int stride = g.stride;
     const int par = a.par, opar = 1 - par;
     const SiteXY c = cb_coords(g, i, par);
-    const int row = i - c.xh;
-    const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
-    const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
-    const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
-    const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
-    const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
-    const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
-    const int tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
-    const int tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+    const SiteNbrs nb = site_nbrs(g, i, c);
+    const int xp = nb.xp, xm = nb.xm, yp = nb.yp, ym = nb.ym, zp = nb.zp, zm = nb.zm, tp = nb.tp, tm = nb.tm;
 
     const char *ll = nullptr;
     if constexpr (LL) {
@@ -647,14 +640,9 @@ hop_kernel_tm(const HopArgs a, int xcd_remap, int nt, int wsplit) {
         const int t = t0 + 2 * j;
         const int i = t * g.st + p;
         const SiteXY c = cb_coords(g, i, par);
-        const int row = i - c.xh;
-        const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
-        const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
-        const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
-        const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
-        const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
-        const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
-        const int tp = (t == Lt - 1) ? p : i + g.st;
+        const SiteNbrs nb = site_nbrs(g, i, c);
+        const int xp = nb.xp, xm = nb.xm, yp = nb.yp, ym = nb.ym, zp = nb.zp, zm = nb.zm;
+        const int tp = (t == Lt - 1) ? p : i + g.st;  // = nb.tp, with t known here
         const int tm = (t == 0) ? (Lt - 1) * g.st + p : i - g.st;
         if constexpr (LL) {
             if (j > 0) __syncthreads();  // every wave has read the previous step's links
@@ -807,25 +795,22 @@ __global__ void __launch_bounds__(320) hop_kernel_ds(const HopArgs a, int xcd_re
         const int par = a.par, opar = 1 - par;
         const SiteXY c = cb_coords(g, i, par);
         const R one = R(1);
+        // each wave forms only the pair of neighbours of its direction
         if (wv == 1) {
-            const int row = i - c.xh;
-            const int xp = row + ((c.xh + c.b == g.Lxh) ? 0 : c.xh + c.b);
-            const int xm = row + ((c.xh + c.b == 0) ? g.Lxh - 1 : c.xh + c.b - 1);
-            hop_dir<SP, GP, 1, NE, G5, LNT, 0, true>(acc, a, act, rhs, xp, par, i, one, stride);
-            hop_dir<SP, GP, 1, NE, G5, LNT, 0, false>(acc, a, act, rhs, xm, opar, xm, one, stride);
+            const SiteNbrs nb = site_nbrs(g, i, c);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 0, true>(acc, a, act, rhs, nb.xp, par, i, one, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 0, false>(acc, a, act, rhs, nb.xm, opar, nb.xm, one, stride);
         } else if (wv == 2) {
-            const int yp = (c.y == g.L[1] - 1) ? i - (g.L[1] - 1) * g.sy : i + g.sy;
-            const int ym = (c.y == 0) ? i + (g.L[1] - 1) * g.sy : i - g.sy;
-            hop_dir<SP, GP, 1, NE, G5, LNT, 1, true>(acc, a, act, rhs, yp, par, i, one, stride);
-            hop_dir<SP, GP, 1, NE, G5, LNT, 1, false>(acc, a, act, rhs, ym, opar, ym, one, stride);
+            const SiteNbrs nb = site_nbrs(g, i, c);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 1, true>(acc, a, act, rhs, nb.yp, par, i, one, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 1, false>(acc, a, act, rhs, nb.ym, opar, nb.ym, one, stride);
         } else if (wv == 3) {
-            const int zp = (c.z == g.L[2] - 1) ? i - (g.L[2] - 1) * g.sz : i + g.sz;
-            const int zm = (c.z == 0) ? i + (g.L[2] - 1) * g.sz : i - g.sz;
-            hop_dir<SP, GP, 1, NE, G5, LNT, 2, true>(acc, a, act, rhs, zp, par, i, one, stride);
-            hop_dir<SP, GP, 1, NE, G5, LNT, 2, false>(acc, a, act, rhs, zm, opar, zm, one, stride);
+            const SiteNbrs nb = site_nbrs(g, i, c);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 2, true>(acc, a, act, rhs, nb.zp, par, i, one, stride);
+            hop_dir<SP, GP, 1, NE, G5, LNT, 2, false>(acc, a, act, rhs, nb.zm, opar, nb.zm, one, stride);
         } else {
-            const int tp = (c.t == g.L[3] - 1) ? i - (g.L[3] - 1) * g.st : i + g.st;
-            const int tm = (c.t == 0) ? i + (g.L[3] - 1) * g.st : i - g.st;
+            const SiteNbrs nb = site_nbrs(g, i, c);
+            const int tp = nb.tp, tm = nb.tm;
             const R sgn_tf = (NE == 6 && c.t == g.L[3] - 1) ? -one : one;
             const R sgn_tb = (NE == 6 && c.t == 0) ? -one : one;
             hop_dir<SP, GP, 1, NE, G5, LNT, 3, true>(acc, a, act, rhs, tp, par, i, sgn_tf, stride);
@@ -887,13 +872,7 @@ static hipError_t launch_hop_k(const HopArgs &a, const LaunchCfg &c, hipStream_t
     // Unused dynamic LDS caps the blocks resident per CU (160 KB of LDS per CU), so fewer
     // sites are in flight per XCD and their neighbour data stays in L2.
     const size_t lds = (size_t)c.lds_kb * 1024;
-    VisitOrder vo;
-    if (c.zblk > 0) {
-        vo.zblk = c.zblk;
-        vo.plane = make_fastdiv((uint32_t)(a.g.Lxh * a.g.L[1]));
-        vo.per_zb = make_fastdiv((uint32_t)(c.zblk * a.g.L[3]));
-        vo.zb = make_fastdiv((uint32_t)c.zblk);
-    }
+    const VisitOrder vo = make_visit_order(a.g, c.zblk);
     switch (c.rpt) {
         case 1: hipLaunchKernelGGL((hop_kernel<SP, GP, 1, NE, G5, LNT, SHX, CLV>), grid, block, lds, s, a, remap, vo, c.wsplit); break;
         case 2:
@@ -922,13 +901,7 @@ template <int SP, int GP, int NE, bool G5, bool SHX>
 static hipError_t launch_hop_ll(const HopArgs &a, const LaunchCfg &c, hipStream_t s) {
     const int ngroups = a.nrhs / c.rpt;
     const dim3 grid(hop_nblocks(a, c) * (ngroups / (c.block / 64))), block(c.block);
-    VisitOrder vo;
-    if (c.zblk > 0) {
-        vo.zblk = c.zblk;
-        vo.plane = make_fastdiv((uint32_t)(a.g.Lxh * a.g.L[1]));
-        vo.per_zb = make_fastdiv((uint32_t)(c.zblk * a.g.L[3]));
-        vo.zb = make_fastdiv((uint32_t)c.zblk);
-    }
+    const VisitOrder vo = make_visit_order(a.g, c.zblk);
     if (c.ldsl == 2) {  // two-row links rebuilt to full links while staging (FP32 / FP16 links)
         if constexpr (NE == 6 && GP != P64) {
             if (c.rpt == 1)

@@ -211,5 +211,8 @@ void timed_launch(wilson_ctx *ctx, int cls, double algorithmic_bytes, F &&launch
 size_t partials_doubles(const Geom &g, int nrhs);
 // Algorithmic bytes of one hop launch (per output site: 8 links + input + output (+ y, z, w)).
 double hop_bytes(const HopArgs &a);
+// host replay of the kernels' site indexing on one lattice (indexcheck.cpp): the number
+// of violations, the first described in `first`
+long long index_check(const int32_t dims[4], std::string &first);
 
 }  // namespace wl
