@@ -108,11 +108,30 @@ class EoCore : public EoMem {
     std::unique_ptr<SolveHostRes> own_host; // host resources, when not lent
     SolveHostRes *host = nullptr;
     const hipEvent_t *ring_ev = nullptr;
-    // captured iteration chunks: one executable graph per solution field, RHS range, kappa
-    // values and mirror slot (the kernels' arguments), with the bookkeeping of one replay
+    // captured iteration chunks: one executable graph per solution field, gauge field
+    // addresses, RHS range, kappa values and mirror slot (the kernels' arguments), with the
+    // bookkeeping of one replay
     bool graphs = false;  // set per call
+    // device addresses a captured chunk reads from the gauge field (links of every
+    // precision, clover blocks) and its link storage: a cached workspace may be bound to
+    // another field, or to a field loaded again at the same host address
+    struct GaugeSig {
+        const void *p[7];
+        int recon;
+        bool operator==(const GaugeSig &o) const {
+            for (int k = 0; k < 7; k++)
+                if (p[k] != o.p[k]) return false;
+            return recon == o.recon;
+        }
+    };
+    GaugeSig gauge_sig() const {
+        return {{G->links(P64), G->links(P32), G->links(P16), G->clovT[0].get(), G->clovT[1].get(),
+                 G->clovTi[0].get(), G->clovTi[1].get()},
+                G->recon};
+    }
     struct Chunk {
         const void *x;
+        GaugeSig gauge;
         int k0, nk, method, slot, iters;
         std::vector<double> kappa;
         hipGraphExec_t exec;
@@ -479,8 +498,9 @@ class EoCore : public EoMem {
     void replay_chunk(Spinor x, int slot) {
         const std::vector<double> kap(kappa.begin() + k0, kappa.begin() + k0 + nk);
         Chunk *c = nullptr;
+        const GaugeSig gs = gauge_sig();
         for (auto &e : chunks)
-            if (e.x == x.data && e.k0 == k0 && e.nk == nk && e.method == method && e.slot == slot &&
+            if (e.x == x.data && e.gauge == gs && e.k0 == k0 && e.nk == nk && e.method == method && e.slot == slot &&
                 e.iters == kGraphChunk && e.kappa == kap) {
                 c = &e;
                 break;
@@ -513,7 +533,7 @@ class EoCore : public EoMem {
                 chunks.erase(chunks.begin());
             }
             // the capture ran nothing: its bookkeeping belongs to each replay
-            chunks.push_back({x.data, k0, nk, method, slot, kGraphChunk, kap, ex, ctx->hop_launch_count - h0,
+            chunks.push_back({x.data, gs, k0, nk, method, slot, kGraphChunk, kap, ex, ctx->hop_launch_count - h0,
                               ctx->bytes_issued - b0, ctx->flops_issued - f0});
             ctx->hop_launch_count = h0;
             ctx->bytes_issued = b0;

@@ -61,3 +61,34 @@ def test_graph_replay_is_bitwise_the_ordinary_path(L, dims, opts, monkeypatch):
     xn, bn = results["1"][-1][0].cpu().numpy(), b.cpu().numpy()
     for j in range(nrhs):
         assert residual(xn[j], bn[j], U.numpy(), k + 0.001 * j, dims) < tol
+
+
+def test_graph_replay_follows_the_bound_gauge_field(L, monkeypatch):
+    """One context solves on two gauge fields of the same shape in turn: its cached solve
+    workspace is bound to each in turn, and a chunk captured on one field must not be
+    replayed on the other."""
+    dims, k, tol = (8, 8, 8, 8), 0.12, 1e-10
+    Us = [inputs.gauge_field(dims, eps=e, seed=s) for e, s in ((0.3, 1711), (0.2, 1712))]
+    b = inputs.gaussian_source(dims, seed=1713).to(DEV)
+    results = {}
+    for graphs in ("0", "1"):
+        monkeypatch.setenv("WILSON_GRAPHS", graphs)
+        ctx = L.wilson_context_create()
+        gs = [L.wilson_gauge_load(ctx, U.to(DEV), dims) for U in Us]
+        try:
+            xs = []
+            for rep in range(4):
+                x = torch.zeros_like(b)
+                st, _ = L.wilson_solve_ex(ctx, gs[rep % 2], x, b, 1, k, tol)
+                assert st == 0, L.wilson_last_error()
+                xs.append(x.clone())
+            results[graphs] = xs
+        finally:
+            for g in gs:
+                L.wilson_gauge_free(ctx, g)
+            L.wilson_context_destroy(ctx)
+    for xa, xb in zip(results["0"], results["1"]):
+        assert torch.equal(xa, xb)
+    for rep, x in enumerate(results["1"]):
+        U = Us[rep % 2]
+        assert residual(x.cpu().numpy(), b.cpu().numpy(), U.numpy(), k, dims) < tol
