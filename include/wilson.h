@@ -41,6 +41,22 @@
  *   Every int-returning call returns a wilson_status code; no C++ exception crosses
  *   the ABI.  wilson_strerror() gives text, wilson_last_error() the detail of the last
  *   failure on the calling thread.
+ *
+ * ENVIRONMENT (read by the library; none is needed)
+ *   WILSON_TUNE=0          no launch-shape tuning: built-in default shapes.
+ *   WILSON_TUNE_CACHE=path tuned shapes read from this JSON-lines file at start and new
+ *                          ones appended (tuning costs a few hundred ms per new shape).
+ *   WILSON_TUNE_VERBOSE=1  print every timed candidate shape to stderr.
+ *   WILSON_HOP_CFG=block,rpt,xcd,zblk[,lds_kb[,wsplit[,shx[,dsplit[,ldsl[,tm]]]]]]
+ *                          pin the parity-hop launch shape of contexts created after it
+ *                          is set (testing).
+ *   WILSON_RECON=18        keep all 18 reals of every link (default: the first two rows
+ *                          when every link is SU(3) to 1e-13, the third rebuilt in the
+ *                          kernels).
+ *   WILSON_GRAPHS=1        on lattices up to 2^16 sites per parity, replay solver
+ *                          iterations in chunks of four from captured HIP graphs (same
+ *                          results bit for bit; measured slower than direct launches on
+ *                          ROCm 7.2, so off by default).
  */
 #ifndef WILSON_H
 #define WILSON_H
