@@ -11,6 +11,11 @@
 //   p = z + beta p
 // The remaining dot products are fused into the operator's epilogue (dslash.hip).
 //
+// This file is compiled without multiply-add contraction (build.py): which product of a
+// complex multiply the compiler would fuse depends on where the scalars come from (scalar
+// registers, or LDS when a kernel runs the finalize of its input), and both forms of a
+// kernel must give the same bits.
+//
 // Reductions accumulate in FP64 whatever the storage precision.  Each block writes
 // one partial per value; a one-block-per-RHS finalize kernel sums the partials in a
 // fixed order (so results are bitwise reproducible run to run and independent of
@@ -18,6 +23,7 @@
 // iteration on the device.
 #include "common.h"
 #include "device.h"
+#include "finalize.h"
 
 namespace wl {
 
@@ -107,13 +113,17 @@ __device__ __forceinline__ void blas_math(const RhsState *st, Opnds<N, R, RX> &o
 // reduced value.
 constexpr int kElemBlock = 1024;
 
-template <int P, int OP>
+template <int P, int OP, bool PRE = false>
 __global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a, int nbs) {
     using R = real_t<P>;
     using S = OpShape<OP>;
     constexpr int CPE = SpinorPack<P>::CPE, NEL = SpinorPack<P>::NEL;
     const int rhs = blockIdx.y;
     const RhsState *st = a.state ? &a.state[rhs] : nullptr;
+    if constexpr (PRE) {  // the finalize of this op's input, then its state (in LDS) is the one used
+        __shared__ RhsState pre_st;
+        st = pre_finalize(a.pre, rhs, &pre_st);
+    }
     if (st && !(st->phase & a.run_mask)) return;
     const int e = blockIdx.x / nbs;
     const int i_raw = (blockIdx.x - e * nbs) * kElemBlock + threadIdx.x;
@@ -150,13 +160,17 @@ __global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a,
 // whole site (x may be FP32 or FP16).
 constexpr int kSiteBlock = 256;
 
-template <int PK, int PX, int OP>
+template <int PK, int PX, int OP, bool PRE = false>
 __global__ void __launch_bounds__(kSiteBlock) blas_site_kernel(const BlasArgs a) {
     using R = real_t<PK>;
     using RX = real_t<PX>;
     using S = OpShape<OP>;
     const int rhs = blockIdx.y;
     const RhsState *st = a.state ? &a.state[rhs] : nullptr;
+    if constexpr (PRE) {  // the finalize of this op's input, then its state (in LDS) is the one used
+        __shared__ RhsState pre_st;
+        st = pre_finalize(a.pre, rhs, &pre_st);
+    }
     if (st && !(st->phase & a.run_mask)) return;
     const int stride = a.g.stride;
     const int i_raw = blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,25 +207,40 @@ int blas_nblocks(const Geom &g, int prec) {
     return (prec == P64 ? 12 : 6) * ((g.Vh + kElemBlock - 1) / kElemBlock);
 }
 
-template <int OP>
+template <int OP, bool PRE>
 static void launch_op_elem(int pk, const BlasArgs &a, hipStream_t s) {
     const int nbs = (a.g.Vh + kElemBlock - 1) / kElemBlock;
     const dim3 grid(blas_nblocks(a.g, pk), a.nrhs), block(kElemBlock);
-    if (pk == P64) hipLaunchKernelGGL((blas_elem_kernel<P64, OP>), grid, block, 0, s, a, nbs);
-    else hipLaunchKernelGGL((blas_elem_kernel<P32, OP>), grid, block, 0, s, a, nbs);
+    if (pk == P64) hipLaunchKernelGGL((blas_elem_kernel<P64, OP, PRE>), grid, block, 0, s, a, nbs);
+    else hipLaunchKernelGGL((blas_elem_kernel<P32, OP, PRE>), grid, block, 0, s, a, nbs);
 }
-template <int PX, int OP>
+template <int PX, int OP, bool PRE>
 static void launch_op_site(const BlasArgs &a, hipStream_t s) {
     const dim3 grid(blas_nblocks(a.g, P16), a.nrhs), block(kSiteBlock);
-    hipLaunchKernelGGL((blas_site_kernel<P16, PX, OP>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((blas_site_kernel<P16, PX, OP, PRE>), grid, block, 0, s, a);
 }
-template <int OP>
-static hipError_t launch_op(int pk, int px, const BlasArgs &a, hipStream_t s) {
-    if ((pk == P64 || pk == P32) && px == pk) launch_op_elem<OP>(pk, a, s);
-    else if (pk == P16 && px == P32) launch_op_site<P32, OP>(a, s);
-    else if (pk == P16 && px == P16) launch_op_site<P16, OP>(a, s);
+template <int OP, bool PRE>
+static hipError_t launch_op_t(int pk, int px, const BlasArgs &a, hipStream_t s) {
+    if ((pk == P64 || pk == P32) && px == pk) launch_op_elem<OP, PRE>(pk, a, s);
+    else if (pk == P16 && px == P32) launch_op_site<P32, OP, PRE>(a, s);
+    else if (pk == P16 && px == P16) launch_op_site<P16, OP, PRE>(a, s);
     else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+// the vector kernels of the BiCGStab iteration may run the finalize of their input first
+template <int OP>
+static hipError_t launch_op(int pk, int px, const BlasArgs &a, hipStream_t s) {
+    if constexpr (OP == BL_S_UPDATE || OP == BL_XR_UPDATE) {
+        if (a.pre.on) {
+            if (a.pre.nblocks > kPreFinMax || a.pre.nv > 3 || !a.pre.partials || a.pre.partials == a.partials ||
+                !a.pre.src || !a.pre.dst || a.pre.src == a.pre.dst)
+                return hipErrorInvalidValue;
+            return launch_op_t<OP, true>(pk, px, a, s);
+        }
+    } else {
+        if (a.pre.on) return hipErrorInvalidValue;
+    }
+    return launch_op_t<OP, false>(pk, px, a, s);
 }
 
 hipError_t launch_blas(int op, const BlasArgs &a, hipStream_t s) {
@@ -230,19 +259,18 @@ hipError_t launch_blas(int op, const BlasArgs &a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------
-// Finalize: sum the per-block partials of one RHS in a fixed order, then the scalar
-// step.  One block per RHS.
-__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
-
-template <int OP>
-__device__ void fin_op(RhsState *st, double a0, double a1, double a2);
-
-// mirror (optional, host-mapped): every RHS's state is copied there after the step, so
-// the host can poll convergence without a device-to-host copy on the stream.
+// Finalize kernel: one block per RHS sums that RHS's partials in a fixed order and runs
+// the scalar step (finalize.h).  Rows a vector kernel could finalize (up to kPreFinMax
+// partials) take one wave, exactly as that kernel does (PreFin); longer rows 256 threads,
+// beyond 4096 partials 1024 (each thread with the same grouping, then the waves in order).
 template <int OP>
 __global__ void __launch_bounds__(1024) finalize_kernel(const double *partials, int nv, int nblocks,
                                                        RhsState *state, int run_mask, RhsState *mirror) {
     const int rhs = blockIdx.x;
+    if (blockDim.x == 64) {
+        fin_rhs_wave(OP, partials, nv, nblocks, rhs, state, run_mask, mirror);
+        return;
+    }
     RhsState *st = &state[rhs];
     if (st->phase & run_mask) {
         __shared__ double tot[3];
@@ -270,110 +298,11 @@ __global__ void __launch_bounds__(1024) finalize_kernel(const double *partials, 
     if (mirror && threadIdx.x == 0) mirror[rhs] = *st;
 }
 
-template <int OP>
-__device__ void fin_op(RhsState *st, const double a0, const double a1, const double a2) {
-    auto fail = [&](int code) {
-        st->phase = PH_FAIL;
-        st->fail = code;
-    };
-    if constexpr (OP == FIN_STORE_AUX) {
-        st->aux = a0;
-    } else if constexpr (OP == FIN_ADD_AUX) {
-        st->aux += a0;
-    } else if constexpr (OP == FIN_BICG_INIT) {
-        st->r2 = a0;
-        st->rhat2 = a0;
-        st->rho_re = a0; st->rho_im = 0.0;
-        st->alpha_re = 1.0; st->alpha_im = 0.0;
-        st->omega_re = 1.0; st->omega_im = 0.0;
-        st->beta_re = 0.0; st->beta_im = 0.0;
-        st->fail = FAIL_NONE;
-        if (!finite(a0)) fail(FAIL_NONFINITE);
-        else if (a0 <= st->stop2) st->phase = PH_DONE;
-        else st->phase = PH_RUN;
-    } else if constexpr (OP == FIN_BICG_ALPHA) {
-        // alpha = rho / <rhat, v>
-        const double den = a0 * a0 + a1 * a1;
-        if (!finite(den)) { fail(FAIL_NONFINITE); return; }
-        if (den == 0.0) { fail(FAIL_BREAKDOWN); return; }
-        st->alpha_re = (st->rho_re * a0 + st->rho_im * a1) / den;
-        st->alpha_im = (st->rho_im * a0 - st->rho_re * a1) / den;
-    } else if constexpr (OP == FIN_BICG_S) {
-        st->s2 = a0;
-        if (!finite(a0)) { fail(FAIL_NONFINITE); return; }
-        if (a0 <= st->stop2) {
-            st->phase = PH_SCONV;  // x += alpha p and stop: omega = 0 makes the last update exactly that
-            st->omega_re = 0.0;
-            st->omega_im = 0.0;
-        }
-    } else if constexpr (OP == FIN_BICG_OMEGA) {
-        if (st->phase != PH_RUN) return;
-        if (!finite(a2) || !finite(a0) || !finite(a1)) { fail(FAIL_NONFINITE); return; }
-        if (a2 == 0.0) { fail(FAIL_BREAKDOWN); return; }
-        st->omega_re = a0 / a2;
-        st->omega_im = a1 / a2;
-        if (st->omega_re == 0.0 && st->omega_im == 0.0) fail(FAIL_BREAKDOWN);
-    } else if constexpr (OP == FIN_BICG_RHO) {
-        st->r2 = a0;
-        st->iter += 1;
-        if (!finite(a0)) { fail(FAIL_NONFINITE); return; }
-        const bool stop = st->phase == PH_SCONV || a0 <= st->stop2;
-        const double rn = sqrt(a1 * a1 + a2 * a2);
-        if (st->phase != PH_SCONV && rn > 1e-30 * sqrt(st->rhat2 * a0)) {
-            // beta = (rho'/rho) (alpha/omega); also on the last iteration of a cycle, so that
-            // a recurrence resumed after its residual was replaced continues from here
-            const double d1 = st->rho_re * st->rho_re + st->rho_im * st->rho_im;
-            const double q1r = (a1 * st->rho_re + a2 * st->rho_im) / d1, q1i = (a2 * st->rho_re - a1 * st->rho_im) / d1;
-            const double d2 = st->omega_re * st->omega_re + st->omega_im * st->omega_im;
-            const double q2r = (st->alpha_re * st->omega_re + st->alpha_im * st->omega_im) / d2;
-            const double q2i = (st->alpha_im * st->omega_re - st->alpha_re * st->omega_im) / d2;
-            st->beta_re = q1r * q2r - q1i * q2i;
-            st->beta_im = q1r * q2i + q1i * q2r;
-            st->rho_re = a1;
-            st->rho_im = a2;
-        } else if (!stop) {
-            fail(FAIL_BREAKDOWN);
-            return;
-        }
-        if (stop) st->phase = PH_DONE;
-    } else if constexpr (OP == FIN_CG_R2) {
-        st->r2 = a0;
-        st->fail = FAIL_NONE;
-        if (!finite(a0)) fail(FAIL_NONFINITE);
-        else if (a0 <= st->stop2) st->phase = PH_DONE;
-        else st->phase = PH_RUN;
-    } else if constexpr (OP == FIN_CG_ZZ) {
-        st->zz = a0;
-        if (!finite(a0)) fail(FAIL_NONFINITE);
-        else if (a0 == 0.0) fail(FAIL_BREAKDOWN);
-    } else if constexpr (OP == FIN_CG_ALPHA) {
-        if (!finite(a0)) { fail(FAIL_NONFINITE); return; }
-        if (a0 == 0.0) { fail(FAIL_BREAKDOWN); return; }
-        st->alpha_re = st->zz / a0;
-        st->alpha_im = 0.0;
-    } else if constexpr (OP == FIN_CG_R) {
-        st->r2 = a0;
-        st->iter += 1;
-        if (!finite(a0)) fail(FAIL_NONFINITE);
-        else if (a0 <= st->stop2) st->phase = PH_DONE;
-    } else if constexpr (OP == FIN_BLOCK_TS) {
-        st->omega_re = a0;
-        st->omega_im = a1;
-        st->aux = a2;
-    } else if constexpr (OP == FIN_CG_BETA) {
-        if (!finite(a0)) { fail(FAIL_NONFINITE); return; }
-        if (st->zz == 0.0) { fail(FAIL_BREAKDOWN); return; }
-        st->beta_re = a0 / st->zz;
-        st->beta_im = 0.0;
-        st->zz = a0;
-    }
-}
-
 hipError_t launch_finalize(int op, const double *partials, int nvals, int nblocks, int nrhs, RhsState *state,
                            int run_mask, hipStream_t s, RhsState *mirror) {
     // a wider block keeps more loads in flight over long partial rows; the block size is a
     // function of the row length alone, so the summation order stays fixed
-    dim3 grid(nrhs), block(nblocks > 4096 ? 1024 : 256);
+    dim3 grid(nrhs), block(nblocks <= kPreFinMax ? 64 : (nblocks > 4096 ? 1024 : 256));
 #define FIN_CASE(X) \
     case X: hipLaunchKernelGGL((finalize_kernel<X>), grid, block, 0, s, partials, nvals, nblocks, state, run_mask, mirror); break;
     switch (op) {

@@ -21,10 +21,14 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
 
 
+# the vector kernels give the same bits in both of their forms only without contraction
+PER_SOURCE = {"blas.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = ["hipcc"] + lang + COMMON + DEVICE + ["-c", os.path.join(HERE, src), "-o", obj]
+    cmd = ["hipcc"] + lang + COMMON + DEVICE + PER_SOURCE.get(src, []) + ["-c", os.path.join(HERE, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -222,6 +222,25 @@ int hop_nblocks(const HopArgs &a, const LaunchCfg &c);
 hipError_t launch_hop(const HopArgs &a, const LaunchCfg &c, hipStream_t s);
 bool hop_cfg_valid(const HopArgs &a, const LaunchCfg &c);
 
+// A finalize run at the start of a vector kernel instead of a launch of its own (short
+// partial rows only): the scalar step `op` on the `nv` values of each right-hand side's
+// `nblocks` partials, applied to the states `src` (phases in run_mask) and stored, with
+// every other field, to `dst`; the kernel then uses the new state.
+struct PreFin {
+    int on;
+    int op;           // FinOp
+    int nv;
+    int nblocks;
+    int run_mask;
+    const double *partials;  // [rhs][nv][nblocks]; not the kernel's own partials buffer
+    const RhsState *src;
+    RhsState *dst;
+};
+// vector kernels run the finalize of their input only for partial rows up to this length
+// (every block of the kernel sums the row again); the finalize kernel sums such rows with
+// one wave, as they do
+constexpr int kPreFinMax = 128;
+
 // BLAS-1 on one parity, nrhs fields; all take the per-rhs state gate.
 struct BlasArgs {
     Geom g;
@@ -232,6 +251,7 @@ struct BlasArgs {
     int pstride;            // 0: the launch's block count
     RhsState *state;
     int run_mask;
+    PreFin pre;             // optional finalize before the op (then the gate and the op use its state)
 };
 enum BlasOp : int {
     BL_P_UPDATE = 0,  // a = p: p = r(b) + beta (p - omega v(c))

@@ -60,6 +60,14 @@ static bool graphs_enabled() {
     return e && std::strcmp(e, "1") == 0;
 }
 constexpr int kAllPhases = PH_IDLE | PH_RUN | PH_SCONV | PH_DONE | PH_FAIL;
+// The BiCGStab iteration lets its s and x/r vector kernels run the finalize of the hop
+// before them (alpha, omega) when the hop's partial rows are short (small lattices, where
+// every launch is short and the gaps between dependent launches dominate): two launches
+// fewer per iteration, the same sums in the same order.  WILSON_FUSE_FIN=0 turns it off.
+static bool prefin_enabled() {
+    const char *e = std::getenv("WILSON_FUSE_FIN");
+    return !(e && std::strcmp(e, "0") == 0);
+}
 
 size_t EoMem::carve(char *base, const Geom &g, int n, int precision, int method) {
     const int P = inner_prec(precision), PX = P == P16 ? P32 : P;
@@ -80,8 +88,10 @@ size_t EoMem::carve(char *base, const Geom &g, int n, int precision, int method)
         bstate = static_cast<BlockState *>(A.take(sizeof(BlockState)));
     }
     partials = static_cast<double *>(A.take(npart * sizeof(double)));
+    partials2 = static_cast<double *>(A.take(partials_doubles(g, n) * sizeof(double)));
     st_in = static_cast<RhsState *>(A.take(sizeof(RhsState) * n));
     st_out = static_cast<RhsState *>(A.take(sizeof(RhsState) * n));
+    st_alt = static_cast<RhsState *>(A.take(sizeof(RhsState) * n));
     bytes = (A.used + 255) & ~size_t(255);
     return bytes;
 }
@@ -112,6 +122,7 @@ class EoCore : public EoMem {
     // addresses, RHS range, kappa values and mirror slot (the kernels' arguments), with the
     // bookkeeping of one replay
     bool graphs = false;  // set per call
+    bool prefin = false;  // vector kernels may run the finalize before them (set per call)
     // device addresses a captured chunk reads from the gauge field (links of every
     // precision, clover blocks) and its link storage: a cached workspace may be bound to
     // another field, or to a field loaded again at the same host address
@@ -133,6 +144,7 @@ class EoCore : public EoMem {
         const void *x;
         GaugeSig gauge;
         int k0, nk, method, slot, iters;
+        bool prefin;
         std::vector<double> kappa;
         hipGraphExec_t exec;
         int64_t hops;
@@ -204,6 +216,8 @@ class EoCore : public EoMem {
     RhsState *mirror_dev(int slot) const { return reinterpret_cast<RhsState *>(host->mirror.dev()) + (size_t)slot * nrhs; }
     RhsState *mirror_host(int slot) const { return reinterpret_cast<RhsState *>(host->mirror.host()) + (size_t)slot * nrhs; }
     double *part() const { return partials; }
+    double *part2() const { return partials2; }
+    RhsState *salt() const { return st_alt; }
     const void *links(int prec) const { return G->links(prec == P64 ? P64 : GP); }
     int lprec(int prec) const { return prec == P64 ? P64 : GP; }
 
@@ -224,14 +238,29 @@ class EoCore : public EoMem {
     }
     int run_hop(HopArgs &a) { return hop(ctx, a, hop_bytes(a)); }
 
-    void finalize(int op, int nv, int nblocks, RhsState *st, int mask, RhsState *mir = nullptr) {
-        WL_HIP(launch_finalize(op, part(), nv, nblocks, nk, S(st), mask, ctx->stream, mir ? mir + k0 : nullptr));
+    // from: the partials to sum (null: the common buffer)
+    void finalize(int op, int nv, int nblocks, RhsState *st, int mask, RhsState *mir = nullptr,
+                  const double *from = nullptr) {
+        WL_HIP(launch_finalize(op, from ? from : part(), nv, nblocks, nk, S(st), mask, ctx->stream,
+                               mir ? mir + k0 : nullptr));
+    }
+    // the finalize `op` of partials `from` run by the vector kernel of `a`, from states src to dst
+    void attach_prefin(BlasArgs &a, int op, int nv, int nblocks, const double *from, RhsState *src, RhsState *dst) const {
+        a.pre.on = 1;
+        a.pre.op = op;
+        a.pre.nv = nv;
+        a.pre.nblocks = nblocks;
+        a.pre.run_mask = PH_RUN;
+        a.pre.partials = from;
+        a.pre.src = S(src);
+        a.pre.dst = S(dst);
     }
 
     // out_e = in_e - k^2 H_eo H_oe in_e  (dag: g5 M g5), optional reduction (finalized by caller)
     // bmx: out_e = b_e - M in_e
+    // red_part: where the reduction's partials go (null: the common buffer)
     int apply_M(Spinor out, Spinor in, Spinor tmpo, bool dag, int red, Spinor w, RhsState *st, int mask,
-                const Spinor *bmx = nullptr) {
+                const Spinor *bmx = nullptr, double *red_part = nullptr) {
         HopArgs h1 = hop_args(1, tmpo, in);
         h1.g5in = dag;
         for (int k = 0; k < nk; k++) h1.cH[k] = 1.0;
@@ -259,6 +288,7 @@ class EoCore : public EoMem {
         h2.w = V(w);
         h2.state = S(st);
         h2.run_mask = mask;
+        if (red_part) h2.partials = red_part;
         return run_hop(h2);
     }
 
@@ -501,7 +531,7 @@ class EoCore : public EoMem {
         const GaugeSig gs = gauge_sig();
         for (auto &e : chunks)
             if (e.x == x.data && e.gauge == gs && e.k0 == k0 && e.nk == nk && e.method == method && e.slot == slot &&
-                e.iters == kGraphChunk && e.kappa == kap) {
+                e.iters == kGraphChunk && e.prefin == prefin && e.kappa == kap) {
                 c = &e;
                 break;
             }
@@ -533,7 +563,7 @@ class EoCore : public EoMem {
                 chunks.erase(chunks.begin());
             }
             // the capture ran nothing: its bookkeeping belongs to each replay
-            chunks.push_back({x.data, gs, k0, nk, method, slot, kGraphChunk, kap, ex, ctx->hop_launch_count - h0,
+            chunks.push_back({x.data, gs, k0, nk, method, slot, kGraphChunk, prefin, kap, ex, ctx->hop_launch_count - h0,
                               ctx->bytes_issued - b0, ctx->flops_issued - f0});
             ctx->hop_launch_count = h0;
             ctx->bytes_issued = b0;
@@ -554,24 +584,35 @@ class EoCore : public EoMem {
             a.a = p.f; a.b = r.f; a.c = v.f;
             run_blas(BL_P_UPDATE, a, vec_bytes(P, 4));
         }
+        // With prefin, the two hops' partials go to their own buffer and the vector kernels
+        // after them run the alpha and omega steps: states sin() -> salt() -> sin().
+        double *hp = prefin ? part2() : part();
         // v = M p, <rhat, v> -> alpha
-        int hb = apply_M(v.f, p.f, tmp.f, false, RED_DOT, rh.f, sin(), PH_RUN);
-        finalize(FIN_BICG_ALPHA, 2, hb, sin(), PH_RUN);
+        int hb = apply_M(v.f, p.f, tmp.f, false, RED_DOT, rh.f, sin(), PH_RUN, nullptr, hp);
+        const bool pa = prefin && hb <= kPreFinMax;
+        if (!pa) finalize(FIN_BICG_ALPHA, 2, hb, sin(), PH_RUN, nullptr, hp);
+        RhsState *st = pa ? salt() : sin();
         {   // s = r - alpha v, |s|^2
             BlasArgs a = blas_args(sin(), PH_RUN);
             a.a = s.f; a.b = r.f; a.c = v.f;
+            if (pa) attach_prefin(a, FIN_BICG_ALPHA, 2, hb, hp, sin(), salt());
             run_blas(BL_S_UPDATE, a, vec_bytes(P, 3));
-            finalize(FIN_BICG_S, 1, nb, sin(), PH_RUN);
+            finalize(FIN_BICG_S, 1, nb, st, PH_RUN);
         }
         // t = M s, <t, s>, |t|^2 -> omega
-        hb = apply_M(t.f, s.f, tmp.f, false, RED_TS, none, sin(), PH_RUN);
-        finalize(FIN_BICG_OMEGA, 3, hb, sin(), PH_RUN);
+        hb = apply_M(t.f, s.f, tmp.f, false, RED_TS, none, st, PH_RUN, nullptr, hp);
+        const bool po = pa && hb <= kPreFinMax;  // the hops of one iteration share their launch shape
+        if (!po) finalize(FIN_BICG_OMEGA, 3, hb, st, PH_RUN, nullptr, hp);
         {   // x += alpha p + omega s; r = s - omega t; |r|^2, <rhat, r> -> beta, rho
-            BlasArgs a = blas_args(sin(), PH_RUN | PH_SCONV);
+            BlasArgs a = blas_args(st, PH_RUN | PH_SCONV);
             a.a = p.f; a.b = s.f; a.c = r.f; a.d = t.f; a.e = rh.f; a.x = x;
+            if (po) attach_prefin(a, FIN_BICG_OMEGA, 3, hb, hp, salt(), sin());
             run_blas(BL_XR_UPDATE, a, vec_bytes(P, 5) + vec_bytes(x.prec, 2));
-            finalize(FIN_BICG_RHO, 3, nb, sin(), PH_RUN | PH_SCONV, mir);
+            if (po) st = sin();
+            finalize(FIN_BICG_RHO, 3, nb, st, PH_RUN | PH_SCONV, mir);
         }
+        if (st != sin())  // (only if the two hops' partial rows differed) the states back to sin()
+            WL_HIP(hipMemcpyAsync(S(sin()), S(st), sizeof(RhsState) * nk, hipMemcpyDeviceToDevice, ctx->stream));
     }
 
     // One block BiCGStab iteration (block.hip has the recurrence); x in FP64.
@@ -691,6 +732,7 @@ int solve_device(wilson_ctx *ctx, const wilson_gauge *G, double *x_canon, const 
     EoCore &C = *core;
     const Geom &g = C.g;
     C.graphs = prm.graphs && !prm.no_tune && graphs_enabled() && g.Vh <= kGraphMaxVh;
+    C.prefin = prefin_enabled();
     C.select(0, nrhs);
     C.kappa.assign(C.nrhs, 0.0);
     std::copy(kappa, kappa + nrhs, C.kappa.begin());
@@ -1083,6 +1125,7 @@ class BatchEngine {
         : ctx(c), G(g), prm(p), n(nslots), slots(nslots) {
         // a caller's workspace holds the batch's device buffers until the batch is destroyed
         C = std::make_unique<EoCore>(c, g, nslots, p.precision, p.method, p.workspace, p.workspace_bytes);
+        C->prefin = prefin_enabled();
         C->kappa.assign(nslots, 0.0);
         delta = p.inner_tol > 0 ? p.inner_tol : (C->P == P32 ? 1e-5 : (C->P == P16 ? 1e-2 : 0.0));
         std::vector<RhsState> h(n);

@@ -47,7 +47,9 @@ struct EoMem {
     FieldBuf r64, tmp64;                      // FP64 outer residual (mixed only)
     FieldBuf r, rh, p, v, s, t, tmp, rf, xin; // inner Krylov fields
     double *partials = nullptr;
+    double *partials2 = nullptr;              // partials of the hops whose finalize a vector kernel runs
     RhsState *st_in = nullptr, *st_out = nullptr;
+    RhsState *st_alt = nullptr;               // states between such a kernel and the iteration's end
     BlockState *bstate = nullptr;             // block BiCGStab only
     size_t bytes = 0;                         // size of the region
     // places every buffer from base (nullptr: sizes only); returns the region's size
