@@ -439,8 +439,13 @@ def run_layouts(args):
     }
 
 
+# the host CPUs this process may use, read before any OpenMP region (with OMP_PROC_BIND the
+# runtime then binds the main thread to one place)
+AFFINITY_AT_START = len(os.sched_getaffinity(0))
+
+
 def host_info(nthr):
-    host = {"cpu_model": None, "logical_cpus": os.cpu_count(), "cpus_in_affinity": len(os.sched_getaffinity(0)),
+    host = {"cpu_model": None, "logical_cpus": os.cpu_count(), "cpus_in_affinity": AFFINITY_AT_START,
             "omp_threads_used": nthr, "omp_proc_bind": os.environ.get("OMP_PROC_BIND"),
             "omp_places": os.environ.get("OMP_PLACES")}
     try:
