@@ -114,7 +114,7 @@ __device__ __forceinline__ void fin_op(RhsState *st, const double a0, const doub
 // run a finalize: inlined into different kernels, the compiler may contract the scalar
 // arithmetic into fused multiply-adds differently, and the two paths would differ in the
 // last bits.
-__device__ __noinline__ void fin_op_rt(int op, RhsState *st, double a0, double a1, double a2) {
+static __device__ __noinline__ void fin_op_rt(int op, RhsState *st, double a0, double a1, double a2) {
 #define FIN_RT(X) \
     case X: fin_op<X>(st, a0, a1, a2); break;
     switch (op) {
