@@ -36,7 +36,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="fp64_32")
-    p.add_argument("--dslash-reps", type=int, default=50)
+    p.add_argument("--dslash-reps", type=int, default=100)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--inner-tol", type=float, default=0.0,
@@ -53,8 +53,8 @@ def parse():
     p.add_argument("--hbm-budget", type=float, default=100e9, help="serving: device bytes for fields + batches")
     p.add_argument("--nslots", type=int, default=12, help="serving: solve slots per gauge field's batch")
     p.add_argument("--latency-samples", type=int, default=100, help="solves of the latency pass (p50/p99)")
-    p.add_argument("--extra-latency-samples", type=int, default=30,
-                   help="latency pass of the other configurations of the default run (8^4 takes 100)")
+    p.add_argument("--extra-latency-samples", type=int, default=100,
+                   help="latency pass of the other configurations of the default run")
     p.add_argument("--no-extras", action="store_true",
                    help="default run: leave out the other configurations (8^4, 48^3x96 mixed x 3, 24^3x48 batched)")
     return p.parse_args()
