@@ -413,6 +413,10 @@ __global__ void __launch_bounds__(kUpdBlock) block_update_kernel(const BlockArgs
 #pragma unroll
     for (int j = 0; j < kMaxBlock; j++) r2[j] = 0.0;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // C is read from LDS in every tile: without this compiler fence the whole s x s
+        // matrix (up to 256 complex doubles) is hoisted out of the loop into registers and
+        // spilled, since stores through global pointers cannot touch LDS
+        __asm__ volatile("" ::: "memory");
         const int c = tile / tps;
         const int site = (tile - c * tps) * kUpdBlock + threadIdx.x;
         if (site >= Vh) continue;
