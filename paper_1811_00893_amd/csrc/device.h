@@ -424,7 +424,8 @@ __host__ __device__ __forceinline__ SiteNbrs site_nbrs(const Geom &g, int i, con
 // t-major then z, so that the spinor read by the +t and -t hops of neighbouring planes is
 // still in L2 when the second hop needs it (in memory order the two uses lie 2*Lz planes
 // apart).  Requires zblk | Lz; with Lxh*Ly a multiple of the block size every block stays
-// inside one plane, so loads stay coalesced.
+// inside one plane, so loads stay coalesced.  With zblk = Lz/8 and the XCD-contiguous block
+// order below, each XCD walks one z-block through every t-slice.
 struct VisitOrder {
     int zblk = 0;
     FastDiv plane, per_zb, zb;  // division by Lxh*Ly, zblk*Lt and zblk

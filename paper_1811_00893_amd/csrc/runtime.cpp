@@ -265,11 +265,15 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         c.xcd = 0;
         cands.push_back(c);
     }
+    // plane blocks of 4 and 8 z-planes, and of Lz/8: with the XCD-contiguous block order that
+    // one gives each of the 8 XCDs one z-range through every t-slice
+    std::vector<int> zblks = {0, 4, 8};
+    if (a.g.L[2] % 8 == 0 && a.g.L[2] / 8 != 4 && a.g.L[2] / 8 != 8) zblks.push_back(a.g.L[2] / 8);
     for (int shx : {0, 1})
         for (int wsplit : {0, 1})
             for (int block : {64, 128, 192, 256})
                 for (int rpt : {1, 2, 3, 4})
-                    for (int zblk : {0, 4, 8})
+                    for (int zblk : zblks)
                         for (int lds_kb : {0, 40}) {
                             if (wsplit && a.nrhs == 1) continue;
                             LaunchCfg c;
@@ -286,7 +290,7 @@ static LaunchCfg tune_hop(wilson_ctx *ctx, const HopArgs &a, double *best_ms) {
         for (int block : {128, 192, 256})
             for (int rpt : {1, 2})
                 for (int shx : {0, 1})
-                    for (int zblk : {0, 4, 8}) {
+                    for (int zblk : zblks) {
                         LaunchCfg c;
                         c.block = block;
                         c.rpt = rpt;

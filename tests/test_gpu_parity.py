@@ -349,6 +349,9 @@ def test_full_size_sampled_dslash(L, ctx):
                                  "256,1,1,0,0,0,1", "64,1,1,4,0,0,1", "128,1,1,0,0,1,1", "256,1,1,2,0,0,1",
                                  "320,1,1,0,0,0,0,1", "320,1,0,0,0,0,0,1", "256,1,1,0,0,1,1,0,1",
                                  "128,2,1,2,0,1,0,0,1",
+                                 # one z-plane per block of the visiting order (Lz/8 here: one
+                                 # z-range per XCD), plain and with the wave split
+                                 "64,1,1,1", "256,1,1,1,0,1,1,0,1",
                                  # t-marching over 5 or 1 slices of one t-parity: plain, two RHS per
                                  # lane, lane exchange, wave split with links in LDS, wave split
                                  # in plain block order, four RHS per lane (FP64: two)
