@@ -25,6 +25,29 @@ DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe
 PER_SOURCE = {"blas.hip": ["-ffp-contract=off"]}
 
 
+def resource_usage(src):
+    """VGPRs and scratch bytes per lane of every kernel in one source, from the compiler's
+    kernel-resource-usage remarks for the device code built with the library's flags."""
+    import re
+    cmd = (["hipcc", "-x", "hip"] + COMMON + DEVICE + PER_SOURCE.get(src, []) +
+           ["--cuda-device-only", "-c", os.path.join(HERE, src), "-o", os.devnull,
+            "-Rpass-analysis=kernel-resource-usage"])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {src}\n{r.stdout}\n{r.stderr}")
+    usage, name = {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            usage[name] = {}
+            continue
+        m = re.search(r"remark:\s+(VGPRs|ScratchSize \[bytes/lane\]): (\d+)", line)
+        if m and name:
+            usage[name]["vgprs" if m.group(1) == "VGPRs" else "scratch"] = int(m.group(2))
+    return usage
+
+
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]

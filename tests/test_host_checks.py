@@ -130,3 +130,19 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     assert "AddressSanitizer" not in out and "runtime error:" not in out, out[-4000:]
     assert r.returncode == 0, out[-4000:]
     assert "sanitized host paths ok" in r.stdout
+
+
+def test_vector_and_block_kernels_do_not_spill():
+    """The solver's vector kernels (fused BLAS-1 updates, reductions, finalize) and the block
+    BiCGStab kernels hold one element per thread and an s x s matrix in LDS: none of them
+    needs scratch.  A spill there (the coefficient matrix once went into registers, 256 VGPRs
+    and 868 bytes of scratch per lane, when the field pointers changed address space) slows
+    them 2-4x with no change in results, so only the compiler's resource report shows it."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_1811_00893_amd", "csrc"))
+    import build
+    allowed = {"_ZN2wl17block_gram_kernelILi16EEEvNS_9BlockArgsE"}  # 4x4 tiles of a 16-column block
+    for src in ("blas.hip", "block.hip"):
+        usage = build.resource_usage(src)
+        assert len(usage) >= 5, (src, usage)
+        spills = {k: v for k, v in usage.items() if v.get("scratch", 0) > 0 and k not in allowed}
+        assert not spills, (src, spills)
