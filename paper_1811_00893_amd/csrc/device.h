@@ -134,20 +134,27 @@ __device__ __forceinline__ void ld_elem(Cx<R> *o, const gchar *plane, unsigned o
         for (int k = 0; k < 4; k++) o[k] = {(R)(float)v[2 * k], (R)(float)v[2 * k + 1]};
     }
 }
-template <int P, typename R>
+// element store.  NT (non-temporal) for the hop's output: no launch reads it back, so it
+// should not take L2 lines from the neighbour spinors that are still to be re-read.
+template <typename T, bool NT>
+__device__ __forceinline__ void st_maybe_nt(gchar *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<WL_GLOBAL T *>(p));
+    else *reinterpret_cast<WL_GLOBAL T *>(p) = v;
+}
+template <int P, typename R, bool NT = false>
 __device__ __forceinline__ void st_elem(gchar *plane, unsigned off, const Cx<R> *x) {
     if constexpr (P == P64) {
         dvec2 v;
         v.x = (double)x[0].re;
         v.y = (double)x[0].im;
-        *reinterpret_cast<WL_GLOBAL dvec2 *>(plane + off) = v;
+        st_maybe_nt<dvec2, NT>(plane + off, v);
     } else if constexpr (P == P32) {
         fvec4 v;
         v.x = (float)x[0].re;
         v.y = (float)x[0].im;
         v.z = (float)x[1].re;
         v.w = (float)x[1].im;
-        *reinterpret_cast<WL_GLOBAL fvec4 *>(plane + off) = v;
+        st_maybe_nt<fvec4, NT>(plane + off, v);
     } else {
         hvec8 v;
 #pragma unroll
@@ -155,7 +162,7 @@ __device__ __forceinline__ void st_elem(gchar *plane, unsigned off, const Cx<R> 
             v[2 * k] = (_Float16)(float)x[k].re;
             v[2 * k + 1] = (_Float16)(float)x[k].im;
         }
-        *reinterpret_cast<WL_GLOBAL hvec8 *>(plane + off) = v;
+        st_maybe_nt<hvec8, NT>(plane + off, v);
     }
 }
 // link element.  NT (non-temporal) when a launch reads each link once, so links do not
@@ -236,7 +243,7 @@ __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int s
 }
 
 // FP16 encoding of a site: s = max |component| (FP32), h = fp16_rne(fp32(v / s)), s = 0 -> zeros.
-template <int P, typename R>
+template <int P, typename R, bool NT = false>
 __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, int i, const Cx<R> (&v)[12]) {
     constexpr int CPE = SpinorPack<P>::CPE, NEL = SpinorPack<P>::NEL;
     const unsigned off = (unsigned)i * 16u;
@@ -251,12 +258,13 @@ __device__ __forceinline__ void store_site(const Spinor &f, int stride, int r, i
             q[c] = s > 0.f ? Cx<float>{(float)v[c].re / sd, (float)v[c].im / sd} : Cx<float>{0.f, 0.f};
 #pragma unroll
         for (int e = 0; e < NEL; e++)
-            st_elem<P, float>(const_cast<gchar *>(splane(f.data, r * NEL + e, stride)), off, &q[e * CPE]);
-        gptr_w(f.scale)[(size_t)r * stride + i] = s;
+            st_elem<P, float, NT>(const_cast<gchar *>(splane(f.data, r * NEL + e, stride)), off, &q[e * CPE]);
+        if constexpr (NT) __builtin_nontemporal_store(s, gptr_w(f.scale) + (size_t)r * stride + i);
+        else gptr_w(f.scale)[(size_t)r * stride + i] = s;
     } else {
 #pragma unroll
         for (int e = 0; e < NEL; e++)
-            st_elem<P, R>(const_cast<gchar *>(splane(f.data, r * NEL + e, stride)), off, &v[e * CPE]);
+            st_elem<P, R, NT>(const_cast<gchar *>(splane(f.data, r * NEL + e, stride)), off, &v[e * CPE]);
     }
 }
 

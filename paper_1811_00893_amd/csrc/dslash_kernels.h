@@ -306,7 +306,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
 #pragma unroll
         for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
     }
-    if (valid && !a.nostore) store_site<SP, R>(a.out, stride, rhs, i, o);
+    if (valid && !a.nostore) store_site<SP, R, true>(a.out, stride, rhs, i, o);
     if (!valid || a.red == RED_NONE) return;
     if (a.red == RED_NORM2) {
         for (int k = 0; k < 12; k++) red[0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
