@@ -119,23 +119,29 @@ __device__ __forceinline__ const gchar *lplane(const void *base, int plane, int 
     return uniform_ptr(static_cast<const char *>(base) + (size_t)plane * stride * LinkPack<P>::EB);
 }
 
-template <int P, typename R>
+// Loads and stores of data that a launch touches once (the hop's y, z and w operands and
+// its output, links when one launch group covers every right-hand side) are non-temporal
+// (NT), so they do not evict from L2 the neighbour spinors that are still to be re-read.
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_maybe_nt(const gchar *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const WL_GLOBAL T *>(p));
+    else return *reinterpret_cast<const WL_GLOBAL T *>(p);
+}
+template <int P, typename R, bool NT = false>
 __device__ __forceinline__ void ld_elem(Cx<R> *o, const gchar *plane, unsigned off) {
     if constexpr (P == P64) {
-        const dvec2 v = *reinterpret_cast<const WL_GLOBAL dvec2 *>(plane + off);
+        const dvec2 v = ld_maybe_nt<dvec2, NT>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
     } else if constexpr (P == P32) {
-        const fvec4 v = *reinterpret_cast<const WL_GLOBAL fvec4 *>(plane + off);
+        const fvec4 v = ld_maybe_nt<fvec4, NT>(plane + off);
         o[0] = {(R)v.x, (R)v.y};
         o[1] = {(R)v.z, (R)v.w};
     } else {
-        const hvec8 v = *reinterpret_cast<const WL_GLOBAL hvec8 *>(plane + off);
+        const hvec8 v = ld_maybe_nt<hvec8, NT>(plane + off);
 #pragma unroll
         for (int k = 0; k < 4; k++) o[k] = {(R)(float)v[2 * k], (R)(float)v[2 * k + 1]};
     }
 }
-// element store.  NT (non-temporal) for the hop's output: no launch reads it back, so it
-// should not take L2 lines from the neighbour spinors that are still to be re-read.
 template <typename T, bool NT>
 __device__ __forceinline__ void st_maybe_nt(gchar *p, T v) {
     if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<WL_GLOBAL T *>(p));
@@ -165,14 +171,8 @@ __device__ __forceinline__ void st_elem(gchar *plane, unsigned off, const Cx<R> 
         st_maybe_nt<hvec8, NT>(plane + off, v);
     }
 }
-// link element.  NT (non-temporal) when a launch reads each link once, so links do not
-// evict spinors from L2; ordinary loads when several right-hand-side groups read the same
-// links one after another and must find them in L2.
-template <typename T, bool NT>
-__device__ __forceinline__ T ld_maybe_nt(const gchar *p) {
-    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const WL_GLOBAL T *>(p));
-    else return *reinterpret_cast<const WL_GLOBAL T *>(p);
-}
+// link element: NT when a launch reads each link once; ordinary loads when several
+// right-hand-side groups read the same links one after another and must find them in L2.
 template <int P, typename R, bool NT>
 __device__ __forceinline__ void ld_link_elem(Cx<R> *o, const gchar *plane, unsigned off) {
     if constexpr (P == P64) {
@@ -229,14 +229,15 @@ __device__ __forceinline__ void st_link_elem(gchar *plane, unsigned off, const C
 }
 
 // Full site (12 complex) of rhs `r` of a parity field; FP16 values are rescaled.
-template <int P, typename R>
+template <int P, typename R, bool NT = false>
 __device__ __forceinline__ void load_site(Cx<R> (&v)[12], const Spinor &f, int stride, int r, int i) {
     constexpr int CPE = SpinorPack<P>::CPE, NEL = SpinorPack<P>::NEL;
     const unsigned off = (unsigned)i * 16u;
 #pragma unroll
-    for (int e = 0; e < NEL; e++) ld_elem<P, R>(&v[e * CPE], splane(f.data, r * NEL + e, stride), off);
+    for (int e = 0; e < NEL; e++) ld_elem<P, R, NT>(&v[e * CPE], splane(f.data, r * NEL + e, stride), off);
     if constexpr (P == P16) {
-        const R s = (R)gptr(f.scale)[(size_t)r * stride + i];
+        const R s = (R)(NT ? __builtin_nontemporal_load(gptr(f.scale) + (size_t)r * stride + i)
+                           : gptr(f.scale)[(size_t)r * stride + i]);
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] = cscale(v[c], s);
     }

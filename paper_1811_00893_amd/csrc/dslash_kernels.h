@@ -285,7 +285,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
             o[s * 3 + k] = cscale(v, cH);
         }
     if (a.has_y) {
-        if (!(PRE & 1)) load_site<SP, R>(yv, a.y, stride, rhs, i);
+        if (!(PRE & 1)) load_site<SP, R, true>(yv, a.y, stride, rhs, i);
         if (CLV && a.clov_mode == CLV_Y) {  // T y enters the sum; y itself stays the dot partner
             Cx<R> ty[12];
 #pragma unroll
@@ -300,7 +300,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
     }
     if (CLV && a.clov_mode == CLV_ALL) clov_apply<CP, R>(o, a.clov, stride, i);
     if (a.has_z) {
-        if (!(PRE & 2)) load_site<SP, R>(zv, a.z, stride, rhs, i);
+        if (!(PRE & 2)) load_site<SP, R, true>(zv, a.z, stride, rhs, i);
         if (CLV && a.clov_mode == CLV_Z) clov_apply<CP, R>(zv, a.clov, stride, i);
         const R cz = (R)a.cz;
 #pragma unroll
@@ -311,7 +311,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
     if (a.red == RED_NORM2) {
         for (int k = 0; k < 12; k++) red[0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
     } else if (a.red == RED_DOT) {
-        if (!(PRE & 4)) load_site<SP, R>(wv, a.w, stride, rhs, i);
+        if (!(PRE & 4)) load_site<SP, R, true>(wv, a.w, stride, rhs, i);
         for (int k = 0; k < 12; k++) {  // <w, o> = sum conj(w) o
             red[0] += (double)wv[k].re * o[k].re + (double)wv[k].im * o[k].im;
             red[1] += (double)wv[k].re * o[k].im - (double)wv[k].im * o[k].re;
@@ -824,7 +824,7 @@ __global__ void __launch_bounds__(320) hop_kernel_ds(const HopArgs a, int xcd_re
                 part[wv - 1][2 * (s * 3 + k) + 1][lane] = acc[0][s][k].im;
             }
     } else if (a.has_y) {  // z and w are loaded after the barrier (registers)
-        load_site<SP, R>(yv, a.y, stride, rhs, i);
+        load_site<SP, R, true>(yv, a.y, stride, rhs, i);
     }
     __syncthreads();
     if (wv != 0) return;
