@@ -291,11 +291,11 @@ __device__ __forceinline__ void clov_load_block(R (&m)[36], const void *base, in
     for (int e = 0; e < EPB; e++) {
         const gchar *pl = splane(base, blk * EPB + e, stride);
         if constexpr (P == P64) {
-            const dvec2 v = *reinterpret_cast<const WL_GLOBAL dvec2 *>(pl + off);
+            const dvec2 v = ld_maybe_nt<dvec2, true>(pl + off);  // read once per launch
             m[2 * e] = (R)v.x;
             m[2 * e + 1] = (R)v.y;
         } else {
-            const fvec4 v = *reinterpret_cast<const WL_GLOBAL fvec4 *>(pl + off);
+            const fvec4 v = ld_maybe_nt<fvec4, true>(pl + off);
             m[4 * e] = (R)v.x;
             m[4 * e + 1] = (R)v.y;
             m[4 * e + 2] = (R)v.z;
