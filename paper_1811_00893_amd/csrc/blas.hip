@@ -113,7 +113,7 @@ __device__ __forceinline__ void blas_math(const RhsState *st, Opnds<N, R, RX> &o
 // reduced value.
 constexpr int kElemBlock = 1024;
 
-template <int P, int OP, bool PRE = false>
+template <int P, int OP, bool PRE = false, bool NT = false>
 __global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a, int nbs) {
     using R = real_t<P>;
     using S = OpShape<OP>;
@@ -131,19 +131,19 @@ __global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a,
     const unsigned off = (unsigned)(valid ? i_raw : a.g.Vh - 1) * 16u;
     const int plane = rhs * NEL + e, stride = a.g.stride;
     Opnds<CPE, R, R> o;
-    if constexpr (S::LD & SA) ld_elem<P, R>(o.a, splane(a.a.data, plane, stride), off);
-    if constexpr (S::LD & SB) ld_elem<P, R>(o.b, splane(a.b.data, plane, stride), off);
-    if constexpr (S::LD & SC) ld_elem<P, R>(o.c, splane(a.c.data, plane, stride), off);
-    if constexpr (S::LD & SD) ld_elem<P, R>(o.d, splane(a.d.data, plane, stride), off);
-    if constexpr (S::LD & SE) ld_elem<P, R>(o.e, splane(a.e.data, plane, stride), off);
-    if constexpr (S::LD & SX) ld_elem<P, R>(o.x, splane(a.x.data, plane, stride), off);
+    if constexpr (S::LD & SA) ld_elem<P, R, NT>(o.a, splane(a.a.data, plane, stride), off);
+    if constexpr (S::LD & SB) ld_elem<P, R, NT>(o.b, splane(a.b.data, plane, stride), off);
+    if constexpr (S::LD & SC) ld_elem<P, R, NT>(o.c, splane(a.c.data, plane, stride), off);
+    if constexpr (S::LD & SD) ld_elem<P, R, NT>(o.d, splane(a.d.data, plane, stride), off);
+    if constexpr (S::LD & SE) ld_elem<P, R, NT>(o.e, splane(a.e.data, plane, stride), off);
+    if constexpr (S::LD & SX) ld_elem<P, R, NT>(o.x, splane(a.x.data, plane, stride), off);
     double red[3] = {0.0, 0.0, 0.0};
     blas_math<OP, CPE, R, R>(st, o, red);
     if (valid) {
-        if constexpr (S::ST & SA) st_elem<P, R>(const_cast<gchar *>(splane(a.a.data, plane, stride)), off, o.a);
-        if constexpr (S::ST & SB) st_elem<P, R>(const_cast<gchar *>(splane(a.b.data, plane, stride)), off, o.b);
-        if constexpr (S::ST & SC) st_elem<P, R>(const_cast<gchar *>(splane(a.c.data, plane, stride)), off, o.c);
-        if constexpr (S::ST & SX) st_elem<P, R>(const_cast<gchar *>(splane(a.x.data, plane, stride)), off, o.x);
+        if constexpr (S::ST & SA) st_elem<P, R, NT>(const_cast<gchar *>(splane(a.a.data, plane, stride)), off, o.a);
+        if constexpr (S::ST & SB) st_elem<P, R, NT>(const_cast<gchar *>(splane(a.b.data, plane, stride)), off, o.b);
+        if constexpr (S::ST & SC) st_elem<P, R, NT>(const_cast<gchar *>(splane(a.c.data, plane, stride)), off, o.c);
+        if constexpr (S::ST & SX) st_elem<P, R, NT>(const_cast<gchar *>(splane(a.x.data, plane, stride)), off, o.x);
     } else {
         red[0] = red[1] = red[2] = 0.0;
     }
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(kElemBlock) blas_elem_kernel(const BlasArgs a,
 // whole site (x may be FP32 or FP16).
 constexpr int kSiteBlock = 256;
 
-template <int PK, int PX, int OP, bool PRE = false>
+template <int PK, int PX, int OP, bool PRE = false, bool NT = false>
 __global__ void __launch_bounds__(kSiteBlock) blas_site_kernel(const BlasArgs a) {
     using R = real_t<PK>;
     using RX = real_t<PX>;
@@ -177,19 +177,19 @@ __global__ void __launch_bounds__(kSiteBlock) blas_site_kernel(const BlasArgs a)
     const bool valid = i_raw < a.g.Vh;
     const int i = valid ? i_raw : a.g.Vh - 1;
     Opnds<12, R, RX> o;
-    if constexpr (S::LD & SA) load_site<PK, R>(o.a, a.a, stride, rhs, i);
-    if constexpr (S::LD & SB) load_site<PK, R>(o.b, a.b, stride, rhs, i);
-    if constexpr (S::LD & SC) load_site<PK, R>(o.c, a.c, stride, rhs, i);
-    if constexpr (S::LD & SD) load_site<PK, R>(o.d, a.d, stride, rhs, i);
-    if constexpr (S::LD & SE) load_site<PK, R>(o.e, a.e, stride, rhs, i);
-    if constexpr (S::LD & SX) load_site<PX, RX>(o.x, a.x, stride, rhs, i);
+    if constexpr (S::LD & SA) load_site<PK, R, NT>(o.a, a.a, stride, rhs, i);
+    if constexpr (S::LD & SB) load_site<PK, R, NT>(o.b, a.b, stride, rhs, i);
+    if constexpr (S::LD & SC) load_site<PK, R, NT>(o.c, a.c, stride, rhs, i);
+    if constexpr (S::LD & SD) load_site<PK, R, NT>(o.d, a.d, stride, rhs, i);
+    if constexpr (S::LD & SE) load_site<PK, R, NT>(o.e, a.e, stride, rhs, i);
+    if constexpr (S::LD & SX) load_site<PX, RX, NT>(o.x, a.x, stride, rhs, i);
     double red[3] = {0.0, 0.0, 0.0};
     blas_math<OP, 12, R, RX>(st, o, red);
     if (valid) {
-        if constexpr (S::ST & SA) store_site<PK, R>(a.a, stride, rhs, i, o.a);
-        if constexpr (S::ST & SB) store_site<PK, R>(a.b, stride, rhs, i, o.b);
-        if constexpr (S::ST & SC) store_site<PK, R>(a.c, stride, rhs, i, o.c);
-        if constexpr (S::ST & SX) store_site<PX, RX>(a.x, stride, rhs, i, o.x);
+        if constexpr (S::ST & SA) store_site<PK, R, NT>(a.a, stride, rhs, i, o.a);
+        if constexpr (S::ST & SB) store_site<PK, R, NT>(a.b, stride, rhs, i, o.b);
+        if constexpr (S::ST & SC) store_site<PK, R, NT>(a.c, stride, rhs, i, o.c);
+        if constexpr (S::ST & SX) store_site<PX, RX, NT>(a.x, stride, rhs, i, o.x);
     } else {
         red[0] = red[1] = red[2] = 0.0;
     }
@@ -207,16 +207,38 @@ int blas_nblocks(const Geom &g, int prec) {
     return (prec == P64 ? 12 : 6) * ((g.Vh + kElemBlock - 1) / kElemBlock);
 }
 
+// Vectors above this size are loaded and stored non-temporally (NT): about eight of them
+// stream through each BiCGStab iteration, more than the 256 MB Infinity Cache holds, so no
+// kernel finds the previous one's output there, and streaming hints let a copy-shaped
+// kernel move 6.5 instead of 6.1 TB/s.  Smaller vectors keep ordinary loads and stores,
+// so the next kernel of the iteration can find them in the caches.
+constexpr size_t kStreamBytes = (size_t)32 << 20;
+static bool streaming(const BlasArgs &a, int pk) {
+    return (size_t)a.nrhs * spinor_field_bytes(pk, a.g) > kStreamBytes;
+}
 template <int OP, bool PRE>
 static void launch_op_elem(int pk, const BlasArgs &a, hipStream_t s) {
     const int nbs = (a.g.Vh + kElemBlock - 1) / kElemBlock;
     const dim3 grid(blas_nblocks(a.g, pk), a.nrhs), block(kElemBlock);
+    if constexpr (!PRE) {  // (the finalizing variants run on small lattices only)
+        if (streaming(a, pk)) {
+            if (pk == P64) hipLaunchKernelGGL((blas_elem_kernel<P64, OP, false, true>), grid, block, 0, s, a, nbs);
+            else hipLaunchKernelGGL((blas_elem_kernel<P32, OP, false, true>), grid, block, 0, s, a, nbs);
+            return;
+        }
+    }
     if (pk == P64) hipLaunchKernelGGL((blas_elem_kernel<P64, OP, PRE>), grid, block, 0, s, a, nbs);
     else hipLaunchKernelGGL((blas_elem_kernel<P32, OP, PRE>), grid, block, 0, s, a, nbs);
 }
 template <int PX, int OP, bool PRE>
 static void launch_op_site(const BlasArgs &a, hipStream_t s) {
     const dim3 grid(blas_nblocks(a.g, P16), a.nrhs), block(kSiteBlock);
+    if constexpr (!PRE) {
+        if (streaming(a, P16)) {
+            hipLaunchKernelGGL((blas_site_kernel<P16, PX, OP, false, true>), grid, block, 0, s, a);
+            return;
+        }
+    }
     hipLaunchKernelGGL((blas_site_kernel<P16, PX, OP, PRE>), grid, block, 0, s, a);
 }
 template <int OP, bool PRE>

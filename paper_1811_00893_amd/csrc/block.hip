@@ -35,15 +35,18 @@ __device__ __forceinline__ gdvec2p fplane(const void *base, int plane, int strid
 __device__ __forceinline__ gdvec2p fplane_lane(const void *base, int plane, int stride) {
     return gptr(reinterpret_cast<const dvec2 *>(static_cast<const char *>(base) + (size_t)plane * stride * 16u));
 }
+template <bool NT = false>
 __device__ __forceinline__ dcx ldc(gdvec2p p, int i) {
-    const dvec2 v = p[i];
+    const dvec2 v = NT ? __builtin_nontemporal_load(p + i) : p[i];
     return {v.x, v.y};
 }
+template <bool NT = false>
 __device__ __forceinline__ void stc(gdvec2p p, int i, dcx v) {
     dvec2 w;
     w.x = v.re;
     w.y = v.im;
-    const_cast<WL_GLOBAL dvec2 *>(p)[i] = w;
+    if constexpr (NT) __builtin_nontemporal_store(w, const_cast<WL_GLOBAL dvec2 *>(p) + i);
+    else const_cast<WL_GLOBAL dvec2 *>(p)[i] = w;
 }
 
 // ---------------------------------------------------------------------------------
@@ -398,7 +401,7 @@ hipError_t launch_block_solve(int op, BlockArgs a, hipStream_t s) {
 // Block combinations.  A thread takes one 16-byte element (one component of one site)
 // of every right-hand side: it loads the s elements of the operand that is multiplied by
 // the s x s matrix (staged in LDS and read as broadcasts), then produces the s outputs.
-template <int OP>
+template <int OP, bool NT>
 __global__ void __launch_bounds__(kUpdBlock) block_update_kernel(const BlockArgs a) {
     if (!block_running(a)) return;
     const int s = a.s, Vh = a.g.Vh, stride = a.g.stride;
@@ -425,12 +428,12 @@ __global__ void __launch_bounds__(kUpdBlock) block_update_kernel(const BlockArgs
         for (int i = 0; i < kMaxBlock; i++) {
             if (i < s) {
                 if constexpr (OP == BU_S) {
-                    m[i] = ldc(fplane(a.c.data, i * 12 + c, stride), site);          // V_i
+                    m[i] = ldc<NT>(fplane(a.c.data, i * 12 + c, stride), site);          // V_i
                 } else if constexpr (OP == BU_XR) {
-                    m[i] = ldc(fplane(a.a.data, i * 12 + c, stride), site);          // P_i
+                    m[i] = ldc<NT>(fplane(a.a.data, i * 12 + c, stride), site);          // P_i
                 } else {
-                    const dcx p = ldc(fplane(a.a.data, i * 12 + c, stride), site);   // P_i - omega V_i
-                    const dcx v = ldc(fplane(a.c.data, i * 12 + c, stride), site);
+                    const dcx p = ldc<NT>(fplane(a.a.data, i * 12 + c, stride), site);   // P_i - omega V_i
+                    const dcx v = ldc<NT>(fplane(a.c.data, i * 12 + c, stride), site);
                     m[i] = csub(p, cmul(omega, v));
                 }
             }
@@ -443,20 +446,20 @@ __global__ void __launch_bounds__(kUpdBlock) block_update_kernel(const BlockArgs
                 for (int i = 0; i < kMaxBlock; i++)
                     if (i < s) acc = cfma(acc, m[i], C[i * kMaxBlock + j]);
                 if constexpr (OP == BU_S) {
-                    const dcx r = ldc(fplane(a.b.data, j * 12 + c, stride), site);
-                    stc(fplane(a.a.data, j * 12 + c, stride), site, csub(r, acc));
+                    const dcx r = ldc<NT>(fplane(a.b.data, j * 12 + c, stride), site);
+                    stc<NT>(fplane(a.a.data, j * 12 + c, stride), site, csub(r, acc));
                 } else if constexpr (OP == BU_XR) {
-                    const dcx sj = ldc(fplane(a.b.data, j * 12 + c, stride), site);
-                    const dcx tj = ldc(fplane(a.d.data, j * 12 + c, stride), site);
+                    const dcx sj = ldc<NT>(fplane(a.b.data, j * 12 + c, stride), site);
+                    const dcx tj = ldc<NT>(fplane(a.d.data, j * 12 + c, stride), site);
                     gdvec2p xp = fplane(a.x.data, j * 12 + c, stride);
-                    const dcx x = ldc(xp, site);
-                    stc(xp, site, cadd(x, cadd(acc, cmul(omega, sj))));
+                    const dcx x = ldc<NT>(xp, site);
+                    stc<NT>(xp, site, cadd(x, cadd(acc, cmul(omega, sj))));
                     const dcx r = csub(sj, cmul(omega, tj));
-                    stc(fplane(a.c.data, j * 12 + c, stride), site, r);
+                    stc<NT>(fplane(a.c.data, j * 12 + c, stride), site, r);
                     r2[j] += cabs2(r);
                 } else {
-                    const dcx r = ldc(fplane(a.b.data, j * 12 + c, stride), site);
-                    stc(fplane(a.a.data, j * 12 + c, stride), site, cadd(r, acc));
+                    const dcx r = ldc<NT>(fplane(a.b.data, j * 12 + c, stride), site);
+                    stc<NT>(fplane(a.a.data, j * 12 + c, stride), site, cadd(r, acc));
                 }
             }
         }
@@ -467,18 +470,23 @@ __global__ void __launch_bounds__(kUpdBlock) block_update_kernel(const BlockArgs
 hipError_t launch_block_update(int op, BlockArgs a, hipStream_t s) {
     if (a.s < 1 || a.s > kMaxBlock) return hipErrorInvalidValue;
     const int ntiles = 12 * ((a.g.Vh + kUpdBlock - 1) / kUpdBlock);
+    // block vectors beyond 32 MB stream through the caches: non-temporal loads and stores
+    const bool nt = (size_t)a.s * spinor_field_bytes(P64, a.g) > ((size_t)32 << 20);
     switch (op) {
         case BU_S:
             a.nblk = ntiles;
-            hipLaunchKernelGGL(block_update_kernel<BU_S>, dim3(ntiles), dim3(kUpdBlock), 0, s, a);
+            if (nt) hipLaunchKernelGGL((block_update_kernel<BU_S, true>), dim3(ntiles), dim3(kUpdBlock), 0, s, a);
+            else hipLaunchKernelGGL((block_update_kernel<BU_S, false>), dim3(ntiles), dim3(kUpdBlock), 0, s, a);
             break;
         case BU_XR:
             a.nblk = xr_nblocks(a.g);
-            hipLaunchKernelGGL(block_update_kernel<BU_XR>, dim3(a.nblk), dim3(kUpdBlock), 0, s, a);
+            if (nt) hipLaunchKernelGGL((block_update_kernel<BU_XR, true>), dim3(a.nblk), dim3(kUpdBlock), 0, s, a);
+            else hipLaunchKernelGGL((block_update_kernel<BU_XR, false>), dim3(a.nblk), dim3(kUpdBlock), 0, s, a);
             break;
         case BU_P:
             a.nblk = ntiles;
-            hipLaunchKernelGGL(block_update_kernel<BU_P>, dim3(ntiles), dim3(kUpdBlock), 0, s, a);
+            if (nt) hipLaunchKernelGGL((block_update_kernel<BU_P, true>), dim3(ntiles), dim3(kUpdBlock), 0, s, a);
+            else hipLaunchKernelGGL((block_update_kernel<BU_P, false>), dim3(ntiles), dim3(kUpdBlock), 0, s, a);
             break;
         default: return hipErrorInvalidValue;
     }
