@@ -266,8 +266,10 @@ __device__ __forceinline__ void lane_nbr(Cx<real_t<SP>> (&H)[RPT][2][3], const C
 // Epilogue of one output site and right-hand side: gamma5 on the hop result, the factor
 // cH, the y and z terms (with the clover modes), the store and the site's reduction terms.
 // PRE (bits 1, 2, 4): y, z, the dot partner w are already in yv, zv, wv (loaded by the
-// caller); the others are loaded here.
-template <int SP, bool CLV, int PRE>
+// caller); the others are loaded here.  NT: the output and the operands read here are
+// streamed (non-temporal); the small-lattice kernel keeps them cached instead, since the
+// next kernel finds its whole working set in L2.
+template <int SP, bool CLV, int PRE, bool NT = true>
 __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, int rhs,
                                            const Cx<real_t<SP>> (&acc)[4][3], Cx<real_t<SP>> (&yv)[12],
                                            Cx<real_t<SP>> (&zv)[12], Cx<real_t<SP>> (&wv)[12], double (&red)[3],
@@ -285,7 +287,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
             o[s * 3 + k] = cscale(v, cH);
         }
     if (a.has_y) {
-        if (!(PRE & 1)) load_site<SP, R, true>(yv, a.y, stride, rhs, i);
+        if (!(PRE & 1)) load_site<SP, R, NT>(yv, a.y, stride, rhs, i);
         if (CLV && a.clov_mode == CLV_Y) {  // T y enters the sum; y itself stays the dot partner
             Cx<R> ty[12];
 #pragma unroll
@@ -300,18 +302,18 @@ __device__ __forceinline__ void hop_finish(const HopArgs &a, int i, bool valid, 
     }
     if (CLV && a.clov_mode == CLV_ALL) clov_apply<CP, R>(o, a.clov, stride, i);
     if (a.has_z) {
-        if (!(PRE & 2)) load_site<SP, R, true>(zv, a.z, stride, rhs, i);
+        if (!(PRE & 2)) load_site<SP, R, NT>(zv, a.z, stride, rhs, i);
         if (CLV && a.clov_mode == CLV_Z) clov_apply<CP, R>(zv, a.clov, stride, i);
         const R cz = (R)a.cz;
 #pragma unroll
         for (int k = 0; k < 12; k++) o[k] = cadd(o[k], cscale(zv[k], cz));
     }
-    if (valid && !a.nostore) store_site<SP, R, true>(a.out, stride, rhs, i, o);
+    if (valid && !a.nostore) store_site<SP, R, NT>(a.out, stride, rhs, i, o);
     if (!valid || a.red == RED_NONE) return;
     if (a.red == RED_NORM2) {
         for (int k = 0; k < 12; k++) red[0] += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
     } else if (a.red == RED_DOT) {
-        if (!(PRE & 4)) load_site<SP, R, true>(wv, a.w, stride, rhs, i);
+        if (!(PRE & 4)) load_site<SP, R, NT>(wv, a.w, stride, rhs, i);
         for (int k = 0; k < 12; k++) {  // <w, o> = sum conj(w) o
             red[0] += (double)wv[k].re * o[k].re + (double)wv[k].im * o[k].im;
             red[1] += (double)wv[k].re * o[k].im - (double)wv[k].im * o[k].re;
@@ -824,7 +826,7 @@ __global__ void __launch_bounds__(320) hop_kernel_ds(const HopArgs a, int xcd_re
                 part[wv - 1][2 * (s * 3 + k) + 1][lane] = acc[0][s][k].im;
             }
     } else if (a.has_y) {  // z and w are loaded after the barrier (registers)
-        load_site<SP, R, true>(yv, a.y, stride, rhs, i);
+        load_site<SP, R, false>(yv, a.y, stride, rhs, i);
     }
     __syncthreads();
     if (wv != 0) return;
@@ -838,7 +840,7 @@ __global__ void __launch_bounds__(320) hop_kernel_ds(const HopArgs a, int xcd_re
                          ((part[0][e + 1][lane] + part[1][e + 1][lane]) + part[2][e + 1][lane]) + part[3][e + 1][lane]};
         }
     double red[3] = {0.0, 0.0, 0.0};
-    hop_finish<SP, CLV, 1>(a, i, valid, rhs, acc, yv, zv, wd, red, stride);
+    hop_finish<SP, CLV, 1, false>(a, i, valid, rhs, acc, yv, zv, wd, red, stride);
     const int nv = red_nvals(a.red);
     if (nv == 0) return;
     const int ntiles = (int)gridDim.x / a.nrhs;
